@@ -1,0 +1,196 @@
+"""FP64 CPU oracle for the many-orbit SDE integrator.
+
+TEST INFRASTRUCTURE ONLY: the plain, single-threaded definition that the HIP
+library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares
+no code with the HIP path and never imports it.
+
+The arithmetic lives in ``sode_oracle.c`` (plain C, ``-O2 -ffp-contract=off``)
+and ``adjoint.py``; this module only marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "sode_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+MODELS = {"kuramoto": 0, "ou": 1, "gbm": 2, "fhn": 3, "rnn": 4}
+METHODS = {"em": 0, "rk4": 1}
+OBSERVABLES = {"state": 0, "kuramoto_r": 1}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with the flags its header fixes."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+             "-D_DEFAULT_SOURCE", "-Wall", "-Wextra", "-fPIC", "-shared",
+             "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=True)
+        L = ctypes.CDLL(LIB)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        L.oracle_philox.argtypes = [u32p, u32p, u32p]
+        L.oracle_philox.restype = None
+        L.oracle_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32, f64p]
+        L.oracle_box_muller.restype = None
+        L.oracle_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_int32, f64p]
+        L.oracle_normals.restype = None
+        L.oracle_model_dims_ok.argtypes = [ctypes.c_int32] * 4
+        L.oracle_model_dims_ok.restype = ctypes.c_int
+        L.oracle_drift.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_double, f64p, f64p, f64p]
+        L.oracle_drift.restype = None
+        L.oracle_diffusion.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_double, f64p, f64p,
+                                                               f64p, f64p]
+        L.oracle_diffusion.restype = None
+        L.oracle_order_parameter.argtypes = [ctypes.c_int32, f64p]
+        L.oracle_order_parameter.restype = ctypes.c_double
+        L.oracle_integrate.argtypes = (
+            [ctypes.c_int32] * 4
+            + [f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+               ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
+               ctypes.c_uint64, u32p, u64p, ctypes.c_int32, ctypes.c_int32, f64p])
+        L.oracle_integrate.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def philox(ctr, key):
+    """Philox-4x32-10 block for counter ``ctr`` (4 x u32) and ``key`` (2 x u32)."""
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().oracle_philox(c, k, o)
+    return [int(x) for x in o]
+
+
+def box_muller(w0: int, w1: int):
+    o = (ctypes.c_double * 2)()
+    lib().oracle_box_muller(w0 & 0xFFFFFFFF, w1 & 0xFFFFFFFF, o)
+    return float(o[0]), float(o[1])
+
+
+def normals(seed: int, orbit_id: int, step: int, m: int) -> np.ndarray:
+    out = np.zeros(m, dtype=np.float64)
+    lib().oracle_normals(seed, orbit_id, step, m, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def dims_ok(model: str, n: int, m: int, d: int) -> bool:
+    return bool(lib().oracle_model_dims_ok(MODELS[model], n, m, d))
+
+
+def drift(model: str, n: int, m: int, d: int, X, p, t: float = 0.0) -> np.ndarray:
+    X, Xp = _f64(X)
+    p, pp = _f64(p)
+    f = np.zeros(n, dtype=np.float64)
+    lib().oracle_drift(MODELS[model], n, m, d, t, Xp, pp, f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return f
+
+
+def diffusion(model: str, n: int, m: int, d: int, X, p, xi, t: float = 0.0) -> np.ndarray:
+    X, Xp = _f64(X)
+    p, pp = _f64(p)
+    xi, xp = _f64(xi)
+    g = np.zeros(n, dtype=np.float64)
+    lib().oracle_diffusion(MODELS[model], n, m, d, t, Xp, pp, xp,
+                           g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return g
+
+
+def order_parameter(theta) -> float:
+    theta, tp = _f64(theta)
+    return float(lib().oracle_order_parameter(theta.size, tp))
+
+
+def integrate(model: str, n: int, m: int, d: int, X0, p, t0: float, dt: float, nsteps: int,
+              stride: int, seed: int, *, method: str = "em", observable: str = "state",
+              orbit_offset: int = 0, step_offset: int = 0, orbit_ids=None, orbit_seeds=None,
+              p_per_orbit: bool | None = None) -> np.ndarray:
+    """Integrate every orbit; returns out[orbits, nsteps/stride+1, q] in float64."""
+    X0, X0p = _f64(X0)
+    X0 = X0.reshape(-1, n)
+    orbits = X0.shape[0]
+    p, pp = _f64(p)
+    if p_per_orbit is None:
+        p_per_orbit = p.ndim == 2
+    if p_per_orbit:
+        assert p.shape == (orbits, d), (p.shape, orbits, d)
+    else:
+        assert p.size == d
+    nsave = nsteps // stride + 1 if stride > 0 else 0
+    q = 1 if observable == "kuramoto_r" else n
+    out = np.zeros((orbits, max(nsave, 0), q), dtype=np.float64)
+    ids_arr = seeds_arr = None
+    ids_p = ctypes.POINTER(ctypes.c_uint32)()
+    seeds_p = ctypes.POINTER(ctypes.c_uint64)()
+    if orbit_ids is not None:
+        ids_arr = np.ascontiguousarray(orbit_ids, dtype=np.uint32)
+        assert ids_arr.size == orbits
+        ids_p = ids_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    if orbit_seeds is not None:
+        seeds_arr = np.ascontiguousarray(orbit_seeds, dtype=np.uint64)
+        assert seeds_arr.size == orbits
+        seeds_p = seeds_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    rc = lib().oracle_integrate(
+        MODELS[model], n, m, d, X0p, pp, int(bool(p_per_orbit)), orbits, t0, dt, nsteps, stride,
+        seed, orbit_offset, step_offset, ids_p, seeds_p, METHODS[method], OBSERVABLES[observable],
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise ValueError(f"oracle_integrate rejected its arguments (rc={rc})")
+    return out
+
+
+def integrate_parallel(model, n, m, d, X0, p, t0, dt, nsteps, stride, seed, *, threads=8,
+                       orbit_ids=None, orbit_seeds=None, orbit_offset=0, **kw) -> np.ndarray:
+    """Run ``integrate`` on disjoint orbit shards in ``threads`` OS threads.
+
+    Orbits are independent, so sharding changes nothing in the result; each
+    shard passes its global orbit ids so the noise is the same as one call.
+    ctypes releases the GIL for the duration of each C call."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    X0 = np.ascontiguousarray(X0, dtype=np.float64).reshape(-1, n)
+    orbits = X0.shape[0]
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    per = p.ndim == 2
+    bounds = np.linspace(0, orbits, threads + 1).astype(int)
+
+    def run(i):
+        a, b = bounds[i], bounds[i + 1]
+        if a == b:
+            return None
+        ids = None if orbit_ids is None else np.asarray(orbit_ids)[a:b]
+        sds = None if orbit_seeds is None else np.asarray(orbit_seeds)[a:b]
+        off = orbit_offset + a if orbit_ids is None else 0
+        return integrate(model, n, m, d, X0[a:b], p[a:b] if per else p, t0, dt, nsteps, stride,
+                         seed, orbit_ids=ids, orbit_seeds=sds, orbit_offset=off,
+                         p_per_orbit=per, **kw)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = [r for r in ex.map(run, range(threads)) if r is not None]
+    return np.concatenate(parts, axis=0)

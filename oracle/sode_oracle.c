@@ -1,0 +1,333 @@
+/*
+ * sode_oracle.c - FP64 reference integrator for many independent orbits of an
+ * Ito SDE system (Avramidis, Lalik & Akman, "SODECL", arXiv 1908.03869).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, plainly written CPU definition
+ * that the HIP library is checked against.  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it; the library never
+ * does, and this file shares no code, header or constant table with the HIP
+ * sources.
+ *
+ * Build flags: -O2 -ffp-contract=off, no fast-math, glibc libm.  Single
+ * threaded.  Every sum runs in index order.  All arithmetic is IEEE binary64.
+ *
+ * Conventions fixed here where the paper is silent (each is listed with its
+ * reason in the design notes of the repository):
+ *   - the uniform generator is Philox-4x32 with 10 rounds, the counter-based
+ *     family the noise-generator section cites (Salmon et al. 2011);
+ *   - counter = (global step k, orbit id, noise block b, tag 0),
+ *     key = (seed mod 2^32, seed >> 32);
+ *   - U1 = ((x0 >> 8) + 1) * 2^-24 in (0,1],  U2 = (x1 >> 8) * 2^-24 in [0,1);
+ *   - words (x0,x1) give normals 4b and 4b+1 (cos first), (x2,x3) give 4b+2
+ *     and 4b+3; normals with index >= m are dropped;
+ *   - X^0 = X0 at t0 (0-based re-indexing of Eq. 2), t_k = t0 + k*dt;
+ *   - out[o][s] = observable(X^{s*stride}) for s = 0..nsteps/stride, so the
+ *     initial state is saved first.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { M_KURAMOTO = 0, M_OU = 1, M_GBM = 2, M_FHN = 3, M_RNN = 4 };
+enum { METHOD_EM = 0, METHOD_RK4 = 1 };
+enum { OBS_STATE = 0, OBS_KURAMOTO_R = 1 };
+
+/* ------------------------------------------------------------------------ */
+/* Philox-4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), the counter-based
+ * generator family behind the Random123 library that the noise-generator
+ * section (Sec. 2.1.2) names.  One round: two 32x32->64 products of the
+ * even counter words with the published multipliers, then a word shuffle
+ * that XORs the high halves with the odd words and the key.  The key is
+ * advanced by the published Weyl increments between rounds.               */
+static const uint32_t PHILOX_MA = 0xD2511F53u; /* multiplies word 0 */
+static const uint32_t PHILOX_MB = 0xCD9E8D57u; /* multiplies word 2 */
+static const uint32_t WEYL_A = 0x9E3779B9u;    /* key word 0 increment */
+static const uint32_t WEYL_B = 0xBB67AE85u;    /* key word 1 increment */
+
+void oracle_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += WEYL_A;
+            k1 += WEYL_B;
+        }
+        uint64_t prod_a = (uint64_t)PHILOX_MA * (uint64_t)c[0];
+        uint64_t prod_b = (uint64_t)PHILOX_MB * (uint64_t)c[2];
+        uint32_t next[4];
+        next[0] = (uint32_t)(prod_b >> 32) ^ c[1] ^ k0;
+        next[1] = (uint32_t)prod_b;
+        next[2] = (uint32_t)(prod_a >> 32) ^ c[3] ^ k1;
+        next[3] = (uint32_t)prod_a;
+        memcpy(c, next, sizeof c);
+    }
+    memcpy(out, c, sizeof c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Box-Muller transform, Eq. (3) of Sec. 2.1.2: two uniforms give two
+ * independent standard normals, the cosine branch first.  The uniforms are
+ * 24-bit so that they are exact in binary32 as well as binary64; U1 excludes
+ * zero so that the logarithm is finite.                                      */
+void oracle_box_muller(uint32_t w0, uint32_t w1, double out[2])
+{
+    const double two_m24 = 1.0 / 16777216.0;
+    double u1 = (double)((w0 >> 8) + 1u) * two_m24;
+    double u2 = (double)(w1 >> 8) * two_m24;
+    double radius = sqrt(-2.0 * log(u1));
+    double angle = 2.0 * M_PI * u2;
+    out[0] = radius * cos(angle);
+    out[1] = radius * sin(angle);
+}
+
+/* The m standard normals N_j(0,1) that Eq. (2) consumes at global step k of
+ * one orbit.  Eq. (3) is applied repeatedly when m > 2 (Sec. 2.1.2); each
+ * Philox block supplies four words, hence two Box-Muller pairs.              */
+void oracle_normals(uint64_t seed, uint32_t orbit_id, uint32_t step, int32_t m, double* xi)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int32_t nblocks = (m + 3) / 4;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        uint32_t ctr[4] = {step, orbit_id, (uint32_t)b, 0u};
+        uint32_t w[4];
+        double pair[2];
+        oracle_philox(ctr, key, w);
+        for (int half = 0; half < 2; ++half) {
+            oracle_box_muller(w[2 * half], w[2 * half + 1], pair);
+            for (int q = 0; q < 2; ++q) {
+                int32_t j = 4 * b + 2 * half + q;
+                if (j < m)
+                    xi[j] = pair[q];
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Model dimensions (n equations, m noise terms, d parameters).               */
+int oracle_model_dims_ok(int32_t model, int32_t n, int32_t m, int32_t d)
+{
+    if (n <= 0 || m <= 0 || d <= 0)
+        return 0;
+    switch (model) {
+    case M_KURAMOTO: /* p = (K, omega_1..N, p_1..N), footnote of Sec. 2.2.1 */
+        return m == n && d == 2 * n + 1;
+    case M_OU: /* p = (a, mu, s) */
+        return m == n && d == 3;
+    case M_GBM: /* p = (mu, s) */
+        return m == n && d == 2;
+    case M_FHN: /* state (v_1..v_N, w_1..w_N), p = (a, b, eps, D, sigma) */
+        return n % 2 == 0 && m == n / 2 && d == 5;
+    case M_RNN: /* p = (W row-major N x N, b_1..N, sigma) */
+        return m == n && (int64_t)d == (int64_t)n * n + n + 1;
+    default:
+        return 0;
+    }
+}
+
+/* Drift f_i(t, X, p) of Eq. (1).
+ *  Kuramoto: Eq. (5)/(6) with the parameter layout of the footnote of
+ *    Sec. 2.2.1 and the loop of Fig. 5: the sum of sin(X_j - X_i) over every
+ *    j (j = i included) in index order, scaled by K/N, plus omega_i.
+ *  OU: -a (X_i - mu).   GBM: mu X_i.
+ *  FHN chain: v' = v - v^3/3 - w + D (v_{i-1} - 2 v_i + v_{i+1}) with
+ *    no-flux ends, w' = eps (v + a - b w).
+ *  RNN: -X + W tanh(X) + b.                                                  */
+void oracle_drift(int32_t model, int32_t n, int32_t m, int32_t d, double t,
+                  const double* X, const double* p, double* f)
+{
+    (void)t;
+    (void)m;
+    (void)d;
+    switch (model) {
+    case M_KURAMOTO: {
+        double K = p[0];
+        for (int32_t i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int32_t j = 0; j < n; ++j)
+                acc = acc + sin(X[j] - X[i]);
+            acc = acc * (K / (double)n);
+            f[i] = acc + p[1 + i];
+        }
+        break;
+    }
+    case M_OU:
+        for (int32_t i = 0; i < n; ++i)
+            f[i] = -p[0] * (X[i] - p[1]);
+        break;
+    case M_GBM:
+        for (int32_t i = 0; i < n; ++i)
+            f[i] = p[0] * X[i];
+        break;
+    case M_FHN: {
+        int32_t N = n / 2;
+        double a = p[0], b = p[1], eps = p[2], D = p[3];
+        const double* v = X;
+        const double* w = X + N;
+        for (int32_t i = 0; i < N; ++i) {
+            double left = v[i > 0 ? i - 1 : 0];
+            double right = v[i < N - 1 ? i + 1 : N - 1];
+            double lap = left - 2.0 * v[i] + right;
+            f[i] = v[i] - v[i] * v[i] * v[i] / 3.0 - w[i] + D * lap;
+            f[N + i] = eps * (v[i] + a - b * w[i]);
+        }
+        break;
+    }
+    case M_RNN: {
+        const double* W = p;
+        const double* bias = p + (size_t)n * n;
+        double* th = (double*)malloc(sizeof(double) * (size_t)n);
+        for (int32_t j = 0; j < n; ++j)
+            th[j] = tanh(X[j]);
+        for (int32_t i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int32_t j = 0; j < n; ++j)
+                acc = acc + W[(size_t)i * n + j] * th[j];
+            f[i] = -X[i] + acc + bias[i];
+        }
+        free(th);
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+/* Diffusion term sum_j g_ij(t, X, p) N_j of Eq. (1)/(2), without the
+ * sqrt(dt) factor, which the stepper applies (Eq. 2).  All models here have
+ * diagonal noise.  Kuramoto: g_ij = p_i delta_ij with p_i stored after the
+ * frequencies (Fig. 5, sode_system_stoch).                                   */
+void oracle_diffusion(int32_t model, int32_t n, int32_t m, int32_t d, double t,
+                      const double* X, const double* p, const double* xi, double* gx)
+{
+    (void)t;
+    switch (model) {
+    case M_KURAMOTO:
+        for (int32_t i = 0; i < n; ++i)
+            gx[i] = p[d - m + i] * xi[i];
+        break;
+    case M_OU:
+        for (int32_t i = 0; i < n; ++i)
+            gx[i] = p[2] * xi[i];
+        break;
+    case M_GBM:
+        for (int32_t i = 0; i < n; ++i)
+            gx[i] = p[1] * X[i] * xi[i];
+        break;
+    case M_FHN: {
+        int32_t N = n / 2;
+        for (int32_t i = 0; i < N; ++i) {
+            gx[i] = p[4] * xi[i];
+            gx[N + i] = 0.0;
+        }
+        break;
+    }
+    case M_RNN:
+        for (int32_t i = 0; i < n; ++i)
+            gx[i] = p[d - 1] * xi[i];
+        break;
+    default:
+        break;
+    }
+}
+
+/* Complex order parameter of Eq. (7), Sec. 2.3.1: r = |(1/N) sum_j e^{i theta_j}|. */
+double oracle_order_parameter(int32_t n, const double* theta)
+{
+    double c = 0.0, s = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+        c = c + cos(theta[j]);
+        s = s + sin(theta[j]);
+    }
+    return sqrt(c * c + s * s) / (double)n;
+}
+
+static void save_observable(int32_t observable, int32_t n, const double* X, double* dst)
+{
+    if (observable == OBS_KURAMOTO_R)
+        dst[0] = oracle_order_parameter(n, X);
+    else
+        for (int32_t i = 0; i < n; ++i)
+            dst[i] = X[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integrate every orbit.  Per orbit, the Euler-Maruyama recursion of Eq. (2)
+ * (Sec. 2.1.1; one call of the per-step integrator of Fig. 2 per step), or,
+ * for method RK4, the classical four-stage Runge-Kutta scheme applied to the
+ * ODE limit g = 0 (Sec. 1.1 last sentence; Sec. 1.5 lists Runge-Kutta among
+ * the ODE methods).  The state is observed every `stride` steps, the host
+ * loop of Sec. 2.1.4 (Eq. 4) with s = stride.
+ *
+ *   X0  [orbits][n]    p  [orbits][d] (p_per_orbit = 1) or [d] (= 0)
+ *   out [orbits][nsteps/stride + 1][q], q = n (state) or 1 (Kuramoto r)
+ *   orbit id of orbit o = orbit_ids[o], else orbit_offset + o;
+ *   seed of orbit o     = orbit_seeds[o], else seed.
+ * Returns 0, or -1 for an argument error.                                    */
+int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
+                     const double* X0, const double* p, int32_t p_per_orbit,
+                     int64_t orbits, double t0, double dt, int64_t nsteps, int64_t stride,
+                     uint64_t seed, uint64_t orbit_offset, uint64_t step_offset,
+                     const uint32_t* orbit_ids, const uint64_t* orbit_seeds,
+                     int32_t method, int32_t observable, double* out)
+{
+    if (!oracle_model_dims_ok(model, n, m, d) || orbits < 0 || nsteps < 0 || stride < 1 ||
+        nsteps % stride != 0 || (method != METHOD_EM && method != METHOD_RK4))
+        return -1;
+    if (observable == OBS_KURAMOTO_R && model != M_KURAMOTO)
+        return -1;
+    if (step_offset + (uint64_t)nsteps > 4294967296ull)
+        return -1;
+    int64_t nsave = nsteps / stride + 1;
+    int32_t q = observable == OBS_KURAMOTO_R ? 1 : n;
+    double* X = (double*)malloc(sizeof(double) * (size_t)n);
+    double* f = (double*)malloc(sizeof(double) * (size_t)n);
+    double* gx = (double*)malloc(sizeof(double) * (size_t)n);
+    double* xi = (double*)malloc(sizeof(double) * (size_t)m);
+    double* k1 = (double*)malloc(sizeof(double) * (size_t)n);
+    double* k2 = (double*)malloc(sizeof(double) * (size_t)n);
+    double* k3 = (double*)malloc(sizeof(double) * (size_t)n);
+    double* k4 = (double*)malloc(sizeof(double) * (size_t)n);
+    double* Y = (double*)malloc(sizeof(double) * (size_t)n);
+    const double sqdt = sqrt(dt);
+
+    for (int64_t o = 0; o < orbits; ++o) {
+        uint32_t id = orbit_ids ? orbit_ids[o] : (uint32_t)(orbit_offset + (uint64_t)o);
+        uint64_t sd = orbit_seeds ? orbit_seeds[o] : seed;
+        const double* po = p + (p_per_orbit ? (size_t)o * (size_t)d : 0);
+        double* out_o = out + (size_t)o * (size_t)nsave * (size_t)q;
+        memcpy(X, X0 + (size_t)o * (size_t)n, sizeof(double) * (size_t)n);
+        save_observable(observable, n, X, out_o);
+
+        for (int64_t k = 0; k < nsteps; ++k) {
+            double t = t0 + (double)k * dt;
+            if (method == METHOD_EM) {
+                oracle_drift(model, n, m, d, t, X, po, f);
+                oracle_normals(sd, id, (uint32_t)(step_offset + (uint64_t)k), m, xi);
+                oracle_diffusion(model, n, m, d, t, X, po, xi, gx);
+                for (int32_t i = 0; i < n; ++i)
+                    X[i] = X[i] + f[i] * dt + gx[i] * sqdt;
+            } else {
+                oracle_drift(model, n, m, d, t, X, po, k1);
+                for (int32_t i = 0; i < n; ++i)
+                    Y[i] = X[i] + 0.5 * dt * k1[i];
+                oracle_drift(model, n, m, d, t + 0.5 * dt, Y, po, k2);
+                for (int32_t i = 0; i < n; ++i)
+                    Y[i] = X[i] + 0.5 * dt * k2[i];
+                oracle_drift(model, n, m, d, t + 0.5 * dt, Y, po, k3);
+                for (int32_t i = 0; i < n; ++i)
+                    Y[i] = X[i] + dt * k3[i];
+                oracle_drift(model, n, m, d, t + dt, Y, po, k4);
+                for (int32_t i = 0; i < n; ++i)
+                    X[i] = X[i] + (dt / 6.0) * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+            }
+            if ((k + 1) % stride == 0)
+                save_observable(observable, n, X, out_o + (size_t)((k + 1) / stride) * (size_t)q);
+        }
+    }
+    free(X); free(f); free(gx); free(xi);
+    free(k1); free(k2); free(k3); free(k4); free(Y);
+    return 0;
+}

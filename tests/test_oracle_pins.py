@@ -1,0 +1,363 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test ties one part of the oracle to something fixed outside it: published
+known-answer vectors, a third-party implementation, a closed form, an
+invariant, a special case that reduces to a library routine, or a value the
+paper states.  CPU only.
+"""
+import json
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+
+
+# --------------------------------------------------------------------------- Philox
+def _kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(x, 16) for x in line.split()]
+            rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answer_vectors(oracle_lib):
+    """Random123's published known-answer vectors for Philox-4x32-10."""
+    for ctr, key, want in _kat():
+        assert oracle_lib.philox(ctr, key) == want
+
+
+@pytest.fixture(scope="module")
+def rocrand_dump(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND cross-check")
+    exe = str(tmp_path_factory.mktemp("xcheck") / "rocrand_philox_dump")
+    src = os.path.join(HERE, "xcheck", "rocrand_philox_dump.cpp")
+    subprocess.check_call([hipcc, "-O1", "-x", "hip", "--offload-arch=gfx950", "-o", exe, src],
+                          stderr=subprocess.DEVNULL)
+    return exe
+
+
+def test_philox_matches_rocrand(oracle_lib, rocrand_dump):
+    """Bit-equality with rocRAND's open-source Philox-4x32-10 engine (run on
+    the host through its public API) over random counters and keys."""
+    rng = np.random.default_rng(11)
+    rows = rng.integers(0, 2**32, size=(3000, 6), dtype=np.uint64)
+    rows[:1000, 1:4] = rng.integers(0, 64, size=(1000, 3))  # counter shapes the library uses
+    text = "\n".join(" ".join(str(int(x)) for x in r) for r in rows) + "\n"
+    res = subprocess.run([rocrand_dump], input=text, capture_output=True, text=True, check=True)
+    got = [list(map(int, l.split())) for l in res.stdout.strip().splitlines()]
+    assert len(got) == len(rows)
+    for r, g in zip(rows, got):
+        assert oracle_lib.philox([int(x) for x in r[:4]], [int(r[4]), int(r[5])]) == g
+
+
+# --------------------------------------------------------------------------- Box-Muller
+def test_box_muller_closed_form(oracle_lib):
+    """Eq. (3): r1 = sqrt(-2 ln U1) cos(2 pi U2), r2 = sqrt(-2 ln U1) sin(2 pi U2)
+    with U1 = ((w0>>8)+1) 2^-24 and U2 = (w1>>8) 2^-24."""
+    # U1 = 1 -> radius 0.
+    assert oracle_lib.box_muller(0xFFFFFFFF, 0x12345678) == (0.0, 0.0)
+    # U1 = 2^-24 (the smallest), U2 = 0 -> (radius, 0): the cosine comes first.
+    r = math.sqrt(48.0 * math.log(2.0))
+    z = oracle_lib.box_muller(0x000000FF, 0x000000FF)
+    assert z[0] == pytest.approx(r, rel=1e-15) and z[1] == 0.0
+    # U2 = 1/4 -> (0, radius); U2 = 1/2 -> (-radius, 0).
+    u1 = (0x800000 + 1) / 2**24
+    r = math.sqrt(-2.0 * math.log(u1))
+    z = oracle_lib.box_muller(0x80000000, 0x40000000)
+    assert abs(z[0]) < 1e-15 and z[1] == pytest.approx(r, rel=1e-15)
+    z = oracle_lib.box_muller(0x80000000, 0x80000000)
+    assert z[0] == pytest.approx(-r, rel=1e-15) and abs(z[1]) < 1e-15
+    # The low 8 bits of each word are ignored (24-bit uniforms).
+    assert oracle_lib.box_muller(0x12345600, 0x9ABCDE00) == oracle_lib.box_muller(0x123456FF, 0x9ABCDEFF)
+
+
+def test_normals_block_layout(oracle_lib):
+    """Normal 4b+2h+q of a step comes from Philox block b, word pair h."""
+    seed, oid, step = 0x0123456789ABCDEF, 77, 1234
+    xi = oracle_lib.normals(seed, oid, step, 10)
+    for b in range(3):
+        w = oracle_lib.philox([step, oid, b, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        for h in range(2):
+            pair = oracle_lib.box_muller(w[2 * h], w[2 * h + 1])
+            for q in range(2):
+                j = 4 * b + 2 * h + q
+                if j < 10:
+                    assert xi[j] == pair[q]
+
+
+def test_normals_are_standard_normal(oracle_lib):
+    """Moments and Kolmogorov-Smirnov against N(0,1) over 2^20 draws, and no
+    correlation between neighbours in one block or between steps."""
+    m, steps = 64, 16384
+    xs = np.stack([oracle_lib.normals(99, 5, k, m) for k in range(steps)])
+    x = xs.ravel()
+    N = x.size
+    assert abs(x.mean()) < 5 / math.sqrt(N)
+    assert abs(x.var() - 1.0) < 5 * math.sqrt(2.0 / N)
+    assert abs(stats.skew(x)) < 5 * math.sqrt(6.0 / N)
+    assert abs(stats.kurtosis(x)) < 5 * math.sqrt(24.0 / N)
+    assert stats.kstest(x, "norm").pvalue > 1e-4
+    for a, b in ((xs[:, 0::2], xs[:, 1::2]), (xs[:, 0::4], xs[:, 2::4]), (xs[:-1], xs[1:])):
+        c = np.corrcoef(a.ravel(), b.ravel())[0, 1]
+        assert abs(c) < 5 / math.sqrt(a.size)
+
+
+# --------------------------------------------------------------------------- EM on OU
+def test_em_brute_force_three_steps(oracle_lib):
+    """n = 1 Ornstein-Uhlenbeck, three EM steps written out by hand (Eq. 2)."""
+    a, mu, s, dt, x = 1.5, 0.25, 0.7, 0.1, 2.0
+    out = oracle_lib.integrate("ou", 1, 1, 3, [[x]], [a, mu, s], 0.0, dt, 3, 1, 42)
+    for k in range(3):
+        xi = oracle_lib.normals(42, 0, k, 1)[0]
+        x = x + (-a * (x - mu)) * dt + (s * xi) * math.sqrt(dt)
+        assert out[0, k + 1, 0] == x
+
+
+def test_ou_discrete_moments(oracle_lib):
+    """EM on dX = -a (X - mu) dt + s dW: with rho = 1 - a dt the iterates have
+    E X_k = mu + rho^k (X0 - mu) and Var X_k = s^2 dt (1 - rho^{2k}) / (1 - rho^2)."""
+    a, mu, s, dt, x0 = 2.0, 0.5, 0.3, 0.01, 1.0
+    orbits, nsteps, stride = 65536, 200, 50
+    out = oracle_lib.integrate("ou", 1, 1, 3, np.full((orbits, 1), x0), [a, mu, s], 0.0, dt,
+                               nsteps, stride, 2024)
+    rho = 1.0 - a * dt
+    for si in range(1, nsteps // stride + 1):
+        k = si * stride
+        mean = mu + rho**k * (x0 - mu)
+        var = s * s * dt * (1 - rho ** (2 * k)) / (1 - rho * rho)
+        X = out[:, si, 0]
+        assert abs(X.mean() - mean) < 5 * math.sqrt(var / orbits)
+        assert abs(X.var(ddof=1) - var) < 5 * var * math.sqrt(2.0 / (orbits - 1))
+
+
+# --------------------------------------------------------------------------- GBM
+def _brownian(oracle_lib, orbits, dt, nsteps, seed):
+    """W(T) driven by the very normals the integrator draws: OU with a = 0,
+    s = 1 and X0 = 0 accumulates sum_k sqrt(dt) xi_k."""
+    return oracle_lib.integrate("ou", 1, 1, 3, np.zeros((orbits, 1)), [0.0, 0.0, 1.0], 0.0,
+                                dt, nsteps, nsteps, seed)[:, -1, 0]
+
+
+def test_gbm_strong_order_half(oracle_lib):
+    """EM for GBM against the exact solution X0 exp((mu - s^2/2) T + s W(T))
+    on the same Brownian path: strong error ~ dt^{1/2}."""
+    mu, s, x0, T, orbits = 1.0, 0.8, 1.0, 1.0, 2048
+    errs, dts = [], []
+    for L in range(4, 10):
+        nsteps = 2**L
+        dt = T / nsteps
+        X = oracle_lib.integrate("gbm", 1, 1, 2, np.full((orbits, 1), x0), [mu, s], 0.0, dt,
+                                 nsteps, nsteps, 500 + L)[:, -1, 0]
+        W = _brownian(oracle_lib, orbits, dt, nsteps, 500 + L)
+        exact = x0 * np.exp((mu - 0.5 * s * s) * T + s * W)
+        errs.append(np.mean(np.abs(X - exact)))
+        dts.append(dt)
+    slope = np.polyfit(np.log(dts), np.log(errs), 1)[0]
+    assert 0.4 < slope < 0.62, (slope, errs)
+
+
+def test_gbm_weak_mean(oracle_lib):
+    """E X_K = X0 (1 + mu dt)^K exactly for the EM iterates of GBM."""
+    mu, s, x0, dt, K, orbits = 0.5, 0.4, 2.0, 0.01, 100, 65536
+    X = oracle_lib.integrate("gbm", 1, 1, 2, np.full((orbits, 1), x0), [mu, s], 0.0, dt, K, K,
+                             77)[:, -1, 0]
+    mean = x0 * (1 + mu * dt) ** K
+    second = x0 * x0 * ((1 + mu * dt) ** 2 + s * s * dt) ** K
+    se = math.sqrt((second - mean * mean) / orbits)
+    assert abs(X.mean() - mean) < 5 * se
+
+
+# --------------------------------------------------------------------------- ODE limit
+def _adler_exact(psi0, a, b, t):
+    """psi' = a - b sin psi with a > b > 0: tan(psi/2) = (b + c tan(c (t - t*)/2)) / a,
+    c = sqrt(a^2 - b^2)."""
+    c = math.sqrt(a * a - b * b)
+    v0 = (a * math.tan(psi0 / 2) - b) / c
+    tstar = -2.0 * math.atan(v0) / c
+    return 2.0 * math.atan((b + c * math.tan(c * (t - tstar) / 2)) / a)
+
+
+def _circ(x, y):
+    return abs(math.remainder(x - y, 2 * math.pi))
+
+
+@pytest.mark.parametrize("method,dts,order", [("em", (2e-2, 1e-2, 5e-3), 1.0),
+                                              ("rk4", (0.1, 0.05, 0.025), 4.0)])
+def test_kuramoto_two_oscillators_adler(oracle_lib, method, dts, order):
+    """n = 2, g = 0: psi = theta_2 - theta_1 obeys the Adler equation
+    psi' = (omega_2 - omega_1) - K sin psi and theta_1 + theta_2 grows at
+    omega_1 + omega_2.  Euler converges with order 1, RK4 with order 4."""
+    K, w1, w2, T = 3.0, -2.0, 2.0, 2.0
+    th0 = np.array([[0.4, 0.7]])
+    p = workloads.kuramoto_params([K], [[w1, w2]], [[0.0, 0.0]])[0]
+    exact = _adler_exact(0.3, w2 - w1, K, T)
+    errs = []
+    for dt in dts:
+        nsteps = int(round(T / dt))
+        out = oracle_lib.integrate("kuramoto", 2, 2, 5, th0, p, 0.0, dt, nsteps, nsteps, 1,
+                                   method=method)
+        th = out[0, -1]
+        errs.append(_circ(th[1] - th[0], exact))
+        assert th[0] + th[1] == pytest.approx(1.1 + (w1 + w2) * T, abs=1e-12)
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    for r in rates:
+        assert abs(r - order) < 0.1 * order, (rates, errs)
+
+
+# --------------------------------------------------------------------------- drifts
+def test_kuramoto_drift_mean_field_identity(oracle_lib):
+    """sum_j sin(t_j - t_i) = cos t_i sum_j sin t_j - sin t_i sum_j cos t_j."""
+    rng = np.random.default_rng(3)
+    N = 64
+    th = rng.uniform(-50, 50, N)
+    K, om, sg = 2.5, rng.standard_normal(N), rng.uniform(0, 1, N)
+    p = workloads.kuramoto_params([K], om[None], sg[None])[0]
+    f = oracle_lib.drift("kuramoto", N, N, 2 * N + 1, th, p)
+    mf = om + (K / N) * (np.cos(th) * np.sin(th).sum() - np.sin(th) * np.cos(th).sum())
+    np.testing.assert_allclose(f, mf, rtol=0, atol=1e-13)
+    # Identical phases: no coupling.
+    f = oracle_lib.drift("kuramoto", N, N, 2 * N + 1, np.full(N, 1.3), p)
+    np.testing.assert_array_equal(f, om)
+
+
+def test_kuramoto_diffusion_layout(oracle_lib):
+    """g_ij = p_i delta_ij with p_i stored after the frequencies."""
+    N = 5
+    p = workloads.kuramoto_params([1.0], np.arange(N)[None] * 1.0, (10.0 + np.arange(N))[None])[0]
+    xi = np.linspace(-1, 1, N)
+    g = oracle_lib.diffusion("kuramoto", N, N, 2 * N + 1, np.zeros(N), p, xi)
+    np.testing.assert_array_equal(g, (10.0 + np.arange(N)) * xi)
+
+
+def test_order_parameter_special_cases(oracle_lib):
+    """Eq. (7): r = 1 for identical phases, r = 0 for equally spaced phases,
+    r = |cos(phi/2)| for two oscillators at 0 and phi."""
+    assert oracle_lib.order_parameter(np.full(64, -2.0)) == pytest.approx(1.0, abs=1e-15)
+    for N in (3, 4, 64, 100):
+        th = 0.37 + 2 * math.pi * np.arange(N) / N
+        assert oracle_lib.order_parameter(th) < 1e-14
+    for phi in (0.1, 1.0, 2.5):
+        assert oracle_lib.order_parameter([0.0, phi]) == pytest.approx(abs(math.cos(phi / 2)), abs=1e-15)
+
+
+def test_fhn_fixed_point_invariant(oracle_lib):
+    """sigma = 0 and every unit at the fixed point (v*, w*) with
+    v*^3 + 3 (1/b - 1) v* + 3 a / b = 0 and w* = (v* + a)/b: nothing moves."""
+    a, b, eps, D = 0.7, 0.8, 0.08, 0.1
+    roots = np.roots([1.0, 0.0, 3 * (1 / b - 1), 3 * a / b])
+    v = float(roots[np.argmin(np.abs(roots.imag))].real)
+    assert v == pytest.approx(-1.1994, abs=1e-4)
+    w = (v + a) / b
+    N = 6
+    X0 = np.concatenate([np.full(N, v), np.full(N, w)])[None]
+    out = oracle_lib.integrate("fhn", 2 * N, N, 5, X0, [a, b, eps, D, 0.0], 0.0, 1e-2, 1000,
+                               1000, 3)
+    np.testing.assert_allclose(out[0, -1], X0[0], atol=1e-12)
+
+
+def test_fhn_uncoupled_units_independent(oracle_lib):
+    """D = 0, sigma = 0: a chain is the union of its single units."""
+    rng = np.random.default_rng(5)
+    N = 4
+    v0, w0 = rng.normal(-1, 0.5, N), rng.normal(-0.5, 0.5, N)
+    pr = [0.7, 0.8, 0.08, 0.0, 0.0]
+    chain = oracle_lib.integrate("fhn", 2 * N, N, 5, np.concatenate([v0, w0])[None], pr, 0.0,
+                                 1e-2, 500, 500, 1)[0, -1]
+    for i in range(N):
+        one = oracle_lib.integrate("fhn", 2, 1, 5, [[v0[i], w0[i]]], pr, 0.0, 1e-2, 500, 500,
+                                   1)[0, -1]
+        assert chain[i] == one[0] and chain[N + i] == one[1]
+
+
+def test_fhn_laplacian_no_flux(oracle_lib):
+    """The coupling term D (v_{i-1} - 2 v_i + v_{i+1}) with reflected ends sums
+    to zero over the chain (no flux through the boundary)."""
+    rng = np.random.default_rng(8)
+    N = 7
+    X = np.concatenate([rng.normal(0, 1, N), np.zeros(N)])
+    base = oracle_lib.drift("fhn", 2 * N, N, 5, X, [0.7, 0.8, 0.08, 0.0, 0.0])
+    coup = oracle_lib.drift("fhn", 2 * N, N, 5, X, [0.7, 0.8, 0.08, 1.0, 0.0])
+    assert abs((coup - base)[:N].sum()) < 1e-13
+    lap = np.convolve(np.concatenate([[X[0]], X[:N], [X[N - 1]]]), [1, -2, 1], "valid")
+    np.testing.assert_allclose((coup - base)[:N], lap, atol=1e-14)
+
+
+def test_rnn_drift_is_matmul(oracle_lib):
+    """f = -X + W tanh X + b equals numpy's matrix product."""
+    rng = np.random.default_rng(9)
+    n = 24
+    W, b, X = rng.normal(0, 0.3, (n, n)), rng.normal(0, 0.3, n), rng.normal(0, 1, n)
+    p = np.concatenate([W.ravel(), b, [0.05]])
+    f = oracle_lib.drift("rnn", n, n, n * n + n + 1, X, p)
+    np.testing.assert_allclose(f, -X + W @ np.tanh(X) + b, rtol=0, atol=1e-13)
+
+
+def test_rnn_zero_weights_is_ou(oracle_lib):
+    """W = 0: dX = (-X + b) dt + sigma dW, an OU process with a = 1, mu = b."""
+    n, orbits, dt, K = 3, 4096, 0.05, 40
+    b, sg = np.array([0.5, -1.0, 2.0]), 0.3
+    p = np.concatenate([np.zeros(n * n), b, [sg]])
+    out = oracle_lib.integrate("rnn", n, n, n * n + n + 1, np.zeros((orbits, n)), p, 0.0, dt, K,
+                               K, 12)[:, -1]
+    ou = oracle_lib.integrate("ou", 1, 1, 3, np.zeros((orbits * n, 1)), [1.0, 0.0, sg], 0.0,
+                              dt, K, K, 13)
+    rho = 1 - dt
+    for i in range(n):
+        mean = b[i] * (1 - rho**K)
+        var = sg * sg * dt * (1 - rho ** (2 * K)) / (1 - rho * rho)
+        assert abs(out[:, i].mean() - mean) < 5 * math.sqrt(var / orbits)
+        assert abs(out[:, i].var(ddof=1) - var) < 5 * var * math.sqrt(2 / orbits)
+    assert ou.shape == (orbits * n, 2, 1)
+
+
+# --------------------------------------------------------------------------- addressing
+def test_resume_and_shards_bitwise(oracle_lib):
+    """Counter-based noise: 2N steps == N steps then N more with step_offset;
+    one call == two calls over disjoint orbit ranges with orbit_offset."""
+    w = workloads.kuramoto_grid(nK=4, nS=4, n=8, nsteps=200)
+    args = ("kuramoto", 8, 8, 17)
+    full = oracle_lib.integrate(*args, w["X0"], w["p"], 0.0, 1e-3, 200, 100, 5)
+    first = oracle_lib.integrate(*args, w["X0"], w["p"], 0.0, 1e-3, 100, 100, 5)
+    second = oracle_lib.integrate(*args, first[:, -1], w["p"], 0.1, 1e-3, 100, 100, 5,
+                                  step_offset=100)
+    np.testing.assert_array_equal(full[:, 2], second[:, 1])
+    a = oracle_lib.integrate(*args, w["X0"][:7], w["p"][:7], 0.0, 1e-3, 200, 100, 5)
+    b = oracle_lib.integrate(*args, w["X0"][7:], w["p"][7:], 0.0, 1e-3, 200, 100, 5,
+                             orbit_offset=7)
+    np.testing.assert_array_equal(np.concatenate([a, b]), full)
+
+
+# --------------------------------------------------------------------------- paper claim
+@pytest.mark.slow
+def test_e4_coherence_either_side_of_critical_coupling(oracle_lib):
+    """The accuracy section's qualitative outcome for N = 100: incoherence at
+    K = 0.02 < K_c and near-synchrony at K = 0.2 > K_c (here dt = 0.2, the
+    coarsest step of that protocol, 16 realisations)."""
+    with open(os.path.join(GOLDEN, "e4_order_parameter.json")) as f:
+        spec = json.load(f)
+    assert 2 / (5 * math.pi) == pytest.approx(spec["K_c"], abs=1e-4)
+    for case in spec["cases"]:
+        w = workloads.kuramoto_e4(case["K"], realisations=16, level=5)
+        out = oracle_lib.integrate_parallel("kuramoto", 100, 100, 201, w["X0"], w["p"], 0.0,
+                                            w["dt"], w["nsteps"], w["stride"], w["seed"],
+                                            threads=8, observable="kuramoto_r")
+        r_end = out[:, -1, 0].mean()
+        if "r_mean_at_end_below" in case:
+            assert r_end < case["r_mean_at_end_below"], r_end
+        else:
+            assert r_end > case["r_mean_at_end_above"], r_end
