@@ -1,0 +1,186 @@
+"""Benchmark: orbit-steps/s of the stochastic Kuramoto n = 64 ensemble on one GPU.
+
+Workload (the n = 64 grid configuration): 65,536 orbits on a 256 x 256 grid of
+coupling K in [0,4] and noise strength sigma in [0.01, 0.5], omega ~ N(0,1),
+Euler-Maruyama with dt = 1e-3 for 2x10^4 steps, order parameter r saved every
+100 steps, binary32 state.  One benchmark step = one sode_integrate call over
+the whole ensemble (noise generation, coupling, update and saves all inside).
+
+Printed JSON line (rank 0): the driver's contract fields plus
+  roofline      the coupled kernel against the VALU issue roofline,
+  cpu_baseline  the FP64 oracle timed on a bounded sample on the host,
+  plain_fp64    the one-orbit-per-lane FP64 kernel on the same ensemble,
+  error         max |dr| against the oracle on the sampled orbits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X VALU issue roofline.  256 CUs x 4 SIMDs at 2.4 GHz; a SIMD retires
+# 32 lanes of a full-rate binary32 add/mul/FMA per clock, so the chip issues
+# 256 * 4 * 32 * 2.4e9 = 7.86e13 lane-slots/s, which is the published
+# 157.3 TFLOP/s binary32 vector peak counted as one FMA (2 flops) per slot.
+VALU_LANE_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
+# Issue cost, in full-rate slots, of each op class the path executes:
+# transcendentals (sin, cos, log2, sqrt) are quarter rate, 32-bit integer
+# multiplies (high or low half) and binary64 FMAs half rate.
+SLOTS = {"valu": 1.0, "trans": 4.0, "imul": 2.0}
+
+
+def algorithmic_slots_per_orbit_step(n: int) -> dict:
+    """Minimal work of one Euler-Maruyama step of one n-oscillator orbit with
+    pairwise sine coupling (each unordered pair once), Philox-4x32-10 noise
+    and Box-Muller normals; counted from the formulation, not the ISA."""
+    pairs = n * (n - 1) // 2
+    blocks = (n + 3) // 4
+    bm_pairs = (n + 1) // 2
+    counts = {
+        # per pair: one difference, one sine, two accumulations
+        "valu": pairs * 3
+        # per oscillator: scale to revolutions, two FMAs, one add, wrap (3)
+        + n * 7
+        # per Box-Muller pair: two int->float conversions, two scalings,
+        # one radius scaling, two products
+        + bm_pairs * 7
+        # per Philox block: ten rounds of two 3-way XORs
+        + blocks * 20,
+        "trans": pairs + bm_pairs * 4,
+        "imul": blocks * 40,
+    }
+    counts["slots"] = sum(counts[k] * SLOTS[k] for k in SLOTS)
+    return counts
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--baseline-steps", type=int, default=1000,
+                    help="Euler steps for the plain FP64 comparison run")
+    ap.add_argument("--cpu-orbits", type=int, default=4,
+                    help="orbits of the oracle sample (full 2x10^4 steps each)")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(orbits shard trivially by orbit_offset; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    import paper_1908_03869_amd as sode
+
+    dev = torch.device("cuda:0")
+    w = workloads.kuramoto_grid()
+    n, orbits, nsteps, stride = w["n"], w["X0"].shape[0], w["nsteps"], w["stride"]
+    X0 = torch.tensor(w["X0"], dtype=torch.float32, device=dev)
+    p = torch.tensor(w["p"], dtype=torch.float32, device=dev)
+    it = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, observable="kuramoto_r")
+    out = torch.empty((orbits, nsteps // stride + 1, 1), dtype=torch.float32, device=dev)
+
+    def step():
+        it.integrate(X0, p, 0.0, w["dt"], nsteps, stride, w["seed"], out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        step()
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = orbits * nsteps / (ms_per_step * 1e-3)
+
+    work = algorithmic_slots_per_orbit_step(n)
+    achieved = work["slots"] * orbits * nsteps / (kernel_ms * 1e-3)
+    r_gpu = out[:, -1, 0].double().cpu().numpy()
+
+    # Plain FP64 one-orbit-per-lane kernel on the same ensemble (fewer steps;
+    # its per-step cost does not depend on the step count).
+    it64 = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=64, observable="kuramoto_r")
+    X64, p64 = X0.double(), p.double()
+    bsteps = args.baseline_steps
+    out64 = torch.empty((orbits, bsteps // stride + 1, 1), dtype=torch.float64, device=dev)
+    it64.integrate(X64[:256], p64[:256], 0.0, w["dt"], stride, stride, w["seed"])
+    torch.cuda.synchronize()
+    b0 = torch.cuda.Event(enable_timing=True)
+    b1 = torch.cuda.Event(enable_timing=True)
+    b0.record(stream)
+    it64.integrate(X64, p64, 0.0, w["dt"], bsteps, stride, w["seed"], out=out64)
+    b1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = b0.elapsed_time(b1)
+    plain_rate = orbits * bsteps / (plain_ms * 1e-3)
+
+    cpu = None
+    err = None
+    if not args.no_cpu:
+        import oracle
+        rows = w["diagonal"][np.linspace(0, 255, args.cpu_orbits).astype(int)]
+        c0 = time.perf_counter()
+        ref = oracle.integrate("kuramoto", n, n, 2 * n + 1, w["X0"][rows], w["p"][rows], 0.0,
+                               w["dt"], nsteps, stride, w["seed"], orbit_ids=rows,
+                               observable="kuramoto_r")
+        cpu_s = time.perf_counter() - c0
+        cpu = {"value": len(rows) * nsteps / cpu_s, "unit": "orbit*steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{len(rows)} grid-diagonal orbits x {nsteps} steps, FP64, "
+                         f"single-threaded, {cpu_s:.1f} s"}
+        err = float(np.max(np.abs(r_gpu[rows] - ref[:, -1, 0])))
+
+    line = {
+        "metric": "orbit*steps/s (Kuramoto n=64 FP32 Euler-Maruyama ensemble)",
+        "value": value,
+        "unit": "orbit*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "kuramoto_grid_n64", "orbits": orbits, "n": n,
+                   "nsteps": nsteps, "dt": w["dt"], "stride": stride,
+                   "observable": "kuramoto_r", "kernel": "coupled"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                     "peak": VALU_LANE_SLOTS_PER_S / 1e12,
+                     "unit": "T VALU lane-slots/s (1 slot = one binary32 FMA)",
+                     "frac": achieved / VALU_LANE_SLOTS_PER_S,
+                     "traffic": None, "kernel_ms": kernel_ms,
+                     "slots_per_orbit_step": work["slots"]},
+        "cpu_baseline": cpu,
+        "plain_fp64": {"value": plain_rate, "unit": "orbit*steps/s", "nsteps": bsteps,
+                       "speedup_of_value": value / plain_rate},
+        "error": {"max_abs_dr_final": err, "tolerance": 1e-4},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

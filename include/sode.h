@@ -1,0 +1,150 @@
+/*
+ * sode.h - C ABI of libsode, an MI355X (gfx950) library that integrates many
+ * independent orbits of an Ito SDE system at once (the problem of
+ * Avramidis, Lalik & Akman, "SODECL", arXiv 1908.03869).
+ *
+ * The system is Eq. (1) of Sec. 1.1:
+ *     dX_i = f_i(t, X, p) dt + sum_j g_ij(t, X, p) dW_j,   i = 1..n, j = 1..m,
+ * with d parameters p.  Each orbit is one (X0, p, noise stream) triple; the
+ * paper's Python interface (Table 2, Fig. 4) takes the same quantities:
+ * initial states, parameter sets, solver, orbit count, n / d / m, dt, time
+ * span and the number of steps between saved states.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers to arrays are DEVICE pointers (HIP global memory), caller
+ *     owned, contiguous and row-major.  The library never frees them.
+ *   - Floating-point arrays (X0, p, out) have the handle's precision:
+ *     float for precision 32, double for precision 64.
+ *   - Launches are asynchronous on the HIP stream passed as `stream`
+ *     (a hipStream_t; NULL = the default stream).  Argument errors are
+ *     reported synchronously, before any HIP call is made; errors raised by
+ *     the device surface at sode_sync() or at the next call on the handle.
+ *   - A handle is not thread-safe; calls on one handle must be serialised.
+ *   - Every function returns SODE_OK (0) or a negative sode_status.
+ */
+#ifndef SODE_H
+#define SODE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sode_ctx* sode_t; /* opaque, owned by the library */
+
+enum sode_status {
+    SODE_OK = 0,
+    SODE_EINVAL = -1,       /* invalid argument (shape, pointer, option)        */
+    SODE_ENOMEM = -2,       /* allocation of library-owned memory failed        */
+    SODE_EDEVICE = -3,      /* a HIP call or a kernel launch failed             */
+    SODE_EUNSUPPORTED = -4, /* valid request that this build does not implement */
+    SODE_ENONFINITE = -5    /* a saved state was NaN or infinite                */
+};
+
+/*
+ * sode_create - make a handle for one SDE model.
+ *
+ * model  "kuramoto": stochastic Kuramoto network, Eq. (5)/(6) of Sec. 2.2.1
+ *                    (f_i = omega_i + K/N sum_j sin(theta_j - theta_i),
+ *                    g_ij = p_i delta_ij); n = m = N, d = 2N+1,
+ *                    p = (K, omega_1..N, p_1..N) (footnote of Sec. 2.2.1).
+ *        "ou":       Ornstein-Uhlenbeck, dX_i = -a (X_i - mu) dt + s dW_i;
+ *                    m = n, d = 3, p = (a, mu, s).
+ *        "gbm":      geometric Brownian motion, dX_i = mu X_i dt + s X_i dW_i;
+ *                    m = n, d = 2, p = (mu, s).
+ * n, m, d must match the model, else SODE_EINVAL.  On success *out receives
+ * a new handle with default options (precision 32, method EM, observable
+ * "state", kernel auto, per-orbit parameters).  No HIP call is made.
+ */
+int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out);
+
+/*
+ * sode_set_option / sode_get_option - integer options of a handle.
+ *
+ *   "precision"    32 | 64   arithmetic type of the state and of X0/p/out.
+ *   "method"       0 = Euler-Maruyama, Eq. (2) of Sec. 2.1.1 (default);
+ *                  1 = classical RK4 on the ODE limit g = 0 (Sec. 1.1; the
+ *                      Runge-Kutta ODE solver of Sec. 1.5): the diffusion is
+ *                      ignored and no noise is drawn.
+ *   "observable"   0 = state (q = n values per save);
+ *                  1 = Kuramoto order parameter r of Eq. (7), Sec. 2.3.1
+ *                      (q = 1; Kuramoto only).
+ *   "kernel"       0 = auto; 1 = plain (one orbit per lane, any model,
+ *                  either precision); 2 = coupled (Kuramoto, precision 32,
+ *                  method EM, n a multiple of 16 up to 128: 16 lanes per
+ *                  orbit exchange phases through DPP row rotations).
+ *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
+ *                  used by every orbit.
+ * Unknown keys or values give SODE_EINVAL and leave the handle unchanged.
+ */
+int sode_set_option(sode_t h, const char* key, int64_t value);
+int sode_get_option(sode_t h, const char* key, int64_t* value);
+
+/*
+ * sode_integrate - integrate `orbits` orbits for `nsteps` steps of size dt
+ * from time t0 and save the observable every `stride` steps.
+ *
+ *   X0   [orbits][n]            initial states X^0 (Sec. 2.1.1, re-indexed
+ *                               from 0: X^0 = X0 at t0).
+ *   p    [orbits][d] or [d]     parameters (see "shared_params").
+ *   out  [orbits][nsave][q]     nsave = nsteps/stride + 1; out[o][s] is the
+ *                               observable of X^{s*stride}, so out[o][0] is
+ *                               the observable of X0.  Kuramoto phases are
+ *                               returned wrapped to [-pi, pi) by the FP32
+ *                               coupled kernel and unwrapped otherwise.
+ *   nsteps >= 0, stride >= 1, nsteps % stride == 0, else SODE_EINVAL.
+ *   seed  key of the Philox-4x32-10 noise stream (Sec. 2.1.2 names the
+ *         Random123 family).  Normal j of orbit o at step k comes from the
+ *         block with counter (k, o, j/4, 0) and key (seed mod 2^32,
+ *         seed >> 32), words (2h, 2h+1), h = (j/2)%2, through Eq. (3)
+ *         with U1 = ((w0 >> 8) + 1) 2^-24 and U2 = (w1 >> 8) 2^-24 (cosine
+ *         for even j, sine for odd j).
+ * Equivalent to sode_integrate_ex with orbit_offset = step_offset = 0 and no
+ * per-orbit ids or seeds.
+ */
+int sode_integrate(sode_t h, const void* X0, const void* p, int64_t orbits, double t0,
+                   double dt, int64_t nsteps, int64_t stride, uint64_t seed, void* out,
+                   void* stream);
+
+/*
+ * sode_integrate_ex - sode_integrate with explicit noise addressing, so that
+ * any orbit can be replayed bit-exactly, shards of one ensemble can run in
+ * separate calls, and an integration can resume where an earlier one ended.
+ *
+ *   orbit_offset  orbit o uses orbit id orbit_offset + o (mod 2^32) ...
+ *   orbit_ids     ... unless this device array [orbits] (uint32) is given.
+ *   orbit_seeds   device array [orbits] (uint64) of per-orbit seeds, or NULL
+ *                 for `seed` everywhere.
+ *   step_offset   step k of this call uses Philox counter step_offset + k;
+ *                 time is still t_k = t0 + k dt.  step_offset + nsteps must
+ *                 not exceed 2^32, else SODE_EINVAL.
+ * Resuming: calling again with X0 = last saved state, t0 = end time and
+ * step_offset = steps already done continues the same noise path.
+ */
+int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, double t0,
+                      double dt, int64_t nsteps, int64_t stride, uint64_t seed,
+                      uint64_t orbit_offset, uint64_t step_offset, const uint32_t* orbit_ids,
+                      const uint64_t* orbit_seeds, void* out, void* stream);
+
+/*
+ * sode_sync - wait for the handle's last launch and report device errors.
+ * Returns SODE_EDEVICE if the stream reported an error.
+ */
+int sode_sync(sode_t h);
+
+/* sode_destroy - release the handle and everything the library owns for it.
+ * NULL is accepted and ignored. */
+int sode_destroy(sode_t h);
+
+/* sode_strerror - static, NUL-terminated description of a status code. */
+const char* sode_strerror(int status);
+
+/* sode_version - library version as major*10000 + minor*100 + patch. */
+int sode_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SODE_H */

@@ -1,0 +1,46 @@
+// launch.hpp - interface between the C ABI layer and the kernel launchers.
+// Everything here is internal to libsode; arguments have been validated by
+// the ABI layer before any launcher is called.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sode {
+
+enum ModelId : int { kKuramoto = 0, kOU = 1, kGBM = 2, kFHN = 3, kRNN = 4 };
+enum MethodId : int { kEM = 0, kRK4 = 1 };
+enum ObservableId : int { kState = 0, kKuramotoR = 1 };
+
+// One integrate request, already checked for shape and range.
+struct Request {
+    int model;
+    int n, m, d;
+    const void* X0;  // [orbits][n]
+    const void* p;   // [orbits][d] or [d]
+    int p_per_orbit; // 1: row o of p belongs to orbit o; 0: one shared row
+    int64_t orbits;
+    double t0, dt;
+    int64_t nsteps, stride, nsave;
+    uint64_t seed, orbit_offset, step_offset;
+    const uint32_t* orbit_ids;    // device, may be null
+    const uint64_t* orbit_seeds;  // device, may be null
+    int method;
+    int observable;
+    void* out;  // [orbits][nsave][q]
+    hipStream_t stream;
+};
+
+// Largest state dimension of the one-orbit-per-lane kernel.
+constexpr int kPlainMaxN = 128;
+
+// One orbit per lane, any model, binary64 or binary32 (the paper's design:
+// one work-item per orbit).  Returns a hipError_t.
+hipError_t launch_plain_f64(const Request& r);
+hipError_t launch_plain_f32(const Request& r);
+
+// Kuramoto, binary32, Euler-Maruyama: 16 lanes per orbit.
+bool coupled_supports(int n);
+hipError_t launch_kuramoto_coupled_f32(const Request& r);
+
+}  // namespace sode

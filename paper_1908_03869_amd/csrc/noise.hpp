@@ -1,0 +1,130 @@
+// noise.hpp - device-side Brownian increments for the SDE steppers.
+//
+// The paper draws uniforms from the Random123 library and turns them into
+// standard normals with the Box-Muller transform (Sec. 2.1.2, Eq. 3).  Here
+// the generator is Philox-4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11, the
+// paper behind Random123), evaluated statelessly: the block that feeds
+// normals 4b..4b+3 of orbit id `oid` at global step k is
+//     Philox(counter = (k, oid, b, 0), key = (seed mod 2^32, seed >> 32)),
+// so every orbit and step can be regenerated anywhere without stored state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sode {
+
+struct Block4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+// Philox-4x32 round structure from the SC'11 paper: the even words are
+// multiplied by the two round multipliers, the high halves are mixed with
+// the odd words and the round key, and the key advances by the two Weyl
+// constants (the golden ratio and sqrt(3) - 1 scaled to 32 bits).
+__device__ __forceinline__ Block4 philox_4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t key_lo, uint32_t key_hi)
+{
+    constexpr uint32_t kMulEven0 = 0xD2511F53u;
+    constexpr uint32_t kMulEven2 = 0xCD9E8D57u;
+    constexpr uint32_t kWeylLo = 0x9E3779B9u;
+    constexpr uint32_t kWeylHi = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(kMulEven0, c0);
+        const uint32_t lo0 = kMulEven0 * c0;
+        const uint32_t hi2 = __umulhi(kMulEven2, c2);
+        const uint32_t lo2 = kMulEven2 * c2;
+        c0 = hi2 ^ c1 ^ key_lo;
+        c1 = lo2;
+        c2 = hi0 ^ c3 ^ key_hi;
+        c3 = lo0;
+        key_lo += kWeylLo;
+        key_hi += kWeylHi;
+    }
+    return Block4{c0, c1, c2, c3};
+}
+
+// 24-bit uniforms: the first of a pair lies in (0,1] so that its logarithm is
+// finite, the second in [0,1).  Both are exact in binary32 and binary64.
+__device__ __forceinline__ float unit_open_f32(uint32_t w) { return (float)((w >> 8) + 1u) * 0x1p-24f; }
+__device__ __forceinline__ float unit_closed_f32(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+__device__ __forceinline__ double unit_open_f64(uint32_t w) { return (double)((w >> 8) + 1u) * 0x1p-24; }
+__device__ __forceinline__ double unit_closed_f64(uint32_t w) { return (double)(w >> 8) * 0x1p-24; }
+
+// Box-Muller pair, Eq. (3): radius sqrt(-2 ln U1), angle 2 pi U2; cosine
+// branch first.  Binary32 version on the hardware transcendental unit:
+// v_log_f32 returns log2, so -2 ln U1 = -2 ln(2) log2(U1); v_sin/v_cos take
+// their argument in revolutions, so U2 is passed as is.
+__device__ __forceinline__ void box_muller_f32(uint32_t a, uint32_t b, float& z_cos, float& z_sin)
+{
+    constexpr float kMinus2Ln2 = -1.38629436111989061883f;
+    const float u1 = unit_open_f32(a);
+    const float u2 = unit_closed_f32(b);
+    const float radius = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u1));
+    z_cos = radius * __builtin_amdgcn_cosf(u2);
+    z_sin = radius * __builtin_amdgcn_sinf(u2);
+}
+
+// Binary64 version on the correctly rounded library functions; sincospi
+// takes the half-turn count 2 U2 and avoids rounding 2 pi U2 first.
+__device__ __forceinline__ void box_muller_f64(uint32_t a, uint32_t b, double& z_cos, double& z_sin)
+{
+    const double u1 = unit_open_f64(a);
+    const double u2 = unit_closed_f64(b);
+    const double radius = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    z_cos = radius * c;
+    z_sin = radius * s;
+}
+
+template <typename R>
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, R& z_cos, R& z_sin);
+template <>
+__device__ __forceinline__ void box_muller<float>(uint32_t a, uint32_t b, float& zc, float& zs)
+{
+    box_muller_f32(a, b, zc, zs);
+}
+template <>
+__device__ __forceinline__ void box_muller<double>(uint32_t a, uint32_t b, double& zc, double& zs)
+{
+    box_muller_f64(a, b, zc, zs);
+}
+
+// Noise addressing of one orbit: its id (Philox counter word 1) and its key.
+struct Stream {
+    uint32_t oid;
+    uint32_t key_lo, key_hi;
+};
+
+__device__ __forceinline__ Stream orbit_stream(int64_t o, uint64_t seed, uint64_t orbit_offset,
+                                               const uint32_t* __restrict__ ids,
+                                               const uint64_t* __restrict__ seeds)
+{
+    Stream s;
+    s.oid = ids ? ids[o] : (uint32_t)(orbit_offset + (uint64_t)o);
+    const uint64_t sd = seeds ? seeds[o] : seed;
+    s.key_lo = (uint32_t)sd;
+    s.key_hi = (uint32_t)(sd >> 32);
+    return s;
+}
+
+// All m normals of one orbit at global step k, written to xi[0..m).
+template <typename R>
+__device__ __forceinline__ void normals(const Stream& st, uint32_t k, int m, R* xi)
+{
+    for (int b = 0; 4 * b < m; ++b) {
+        const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)b, 0u, st.key_lo, st.key_hi);
+        R z0, z1, z2, z3;
+        box_muller<R>(w.w0, w.w1, z0, z1);
+        box_muller<R>(w.w2, w.w3, z2, z3);
+        const int j = 4 * b;
+        xi[j] = z0;
+        if (j + 1 < m) xi[j + 1] = z1;
+        if (j + 2 < m) xi[j + 2] = z2;
+        if (j + 3 < m) xi[j + 3] = z3;
+    }
+}
+
+}  // namespace sode

@@ -1,0 +1,272 @@
+// sode_abi.cpp - the C ABI of libsode (declared in include/sode.h).
+//
+// Every entry point validates its arguments completely before it makes any
+// HIP call, so argument errors are reported synchronously (and can be tested
+// on a machine without a GPU).  Dispatch then picks a kernel and launches it
+// asynchronously on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "launch.hpp"
+#include "sode.h"
+
+struct sode_ctx {
+    int model;
+    int32_t n, m, d;
+    int precision = 32;
+    int method = sode::kEM;
+    int observable = sode::kState;
+    int kernel = 0;  // 0 auto, 1 plain, 2 coupled
+    int shared_params = 0;
+    hipError_t last_error = hipSuccess;
+    hipStream_t last_stream = nullptr;
+    bool launched = false;
+};
+
+namespace {
+
+constexpr int kVersion = 100;  // 0.1.0
+
+// Upper bound on orbits per call: keeps every grid (16 lanes per orbit in
+// the coupled kernel) below 2^32 work-items.
+constexpr int64_t kMaxOrbits = int64_t(1) << 27;
+
+struct ModelInfo {
+    const char* name;
+    int id;
+};
+constexpr ModelInfo kModels[] = {
+    {"kuramoto", sode::kKuramoto}, {"ou", sode::kOU}, {"gbm", sode::kGBM},
+    {"fhn", sode::kFHN},           {"rnn", sode::kRNN},
+};
+
+// Dimensions (n equations, m noises, d parameters) each model accepts.
+bool dims_match(int model, int32_t n, int32_t m, int32_t d)
+{
+    if (n <= 0 || m <= 0 || d <= 0)
+        return false;
+    switch (model) {
+    case sode::kKuramoto: return m == n && (int64_t)d == 2 * (int64_t)n + 1;
+    case sode::kOU: return m == n && d == 3;
+    case sode::kGBM: return m == n && d == 2;
+    case sode::kFHN: return n % 2 == 0 && m == n / 2 && d == 5;
+    case sode::kRNN: return m == n && (int64_t)d == (int64_t)n * n + n + 1;
+    default: return false;
+    }
+}
+
+int status_of(hipError_t e) { return e == hipSuccess ? SODE_OK : SODE_EDEVICE; }
+
+// Which kernel a request goes to; SODE_EUNSUPPORTED if none can run it.
+int choose_kernel(const sode_ctx* h, int* kernel)
+{
+    const bool coupled_ok = h->model == sode::kKuramoto && h->precision == 32 &&
+                            h->method == sode::kEM && sode::coupled_supports(h->n);
+    const bool plain_ok = h->n <= sode::kPlainMaxN;
+    if (h->kernel == 2) {
+        if (!coupled_ok)
+            return SODE_EUNSUPPORTED;
+        *kernel = 2;
+    } else if (h->kernel == 1) {
+        if (!plain_ok)
+            return SODE_EUNSUPPORTED;
+        *kernel = 1;
+    } else if (coupled_ok) {
+        *kernel = 2;
+    } else if (plain_ok) {
+        *kernel = 1;
+    } else {
+        return SODE_EUNSUPPORTED;
+    }
+    return SODE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sode_version(void) { return kVersion; }
+
+const char* sode_strerror(int status)
+{
+    switch (status) {
+    case SODE_OK: return "success";
+    case SODE_EINVAL: return "invalid argument";
+    case SODE_ENOMEM: return "out of memory";
+    case SODE_EDEVICE: return "HIP device or launch error";
+    case SODE_EUNSUPPORTED: return "unsupported combination of model, size and options";
+    case SODE_ENONFINITE: return "non-finite value in a saved state";
+    default: return "unknown status";
+    }
+}
+
+int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out)
+{
+    if (!model || !out)
+        return SODE_EINVAL;
+    *out = nullptr;
+    int id = -1;
+    for (const ModelInfo& mi : kModels)
+        if (std::strcmp(mi.name, model) == 0)
+            id = mi.id;
+    if (id < 0 || !dims_match(id, n, m, d))
+        return SODE_EINVAL;
+    sode_ctx* h = new (std::nothrow) sode_ctx;
+    if (!h)
+        return SODE_ENOMEM;
+    h->model = id;
+    h->n = n;
+    h->m = m;
+    h->d = d;
+    *out = h;
+    return SODE_OK;
+}
+
+int sode_set_option(sode_t h, const char* key, int64_t value)
+{
+    if (!h || !key)
+        return SODE_EINVAL;
+    if (std::strcmp(key, "precision") == 0) {
+        if (value != 32 && value != 64)
+            return SODE_EINVAL;
+        h->precision = (int)value;
+    } else if (std::strcmp(key, "method") == 0) {
+        if (value != sode::kEM && value != sode::kRK4)
+            return SODE_EINVAL;
+        h->method = (int)value;
+    } else if (std::strcmp(key, "observable") == 0) {
+        if (value != sode::kState && value != sode::kKuramotoR)
+            return SODE_EINVAL;
+        if (value == sode::kKuramotoR && h->model != sode::kKuramoto)
+            return SODE_EINVAL;
+        h->observable = (int)value;
+    } else if (std::strcmp(key, "kernel") == 0) {
+        if (value < 0 || value > 2)
+            return SODE_EINVAL;
+        h->kernel = (int)value;
+    } else if (std::strcmp(key, "shared_params") == 0) {
+        if (value != 0 && value != 1)
+            return SODE_EINVAL;
+        h->shared_params = (int)value;
+    } else {
+        return SODE_EINVAL;
+    }
+    return SODE_OK;
+}
+
+int sode_get_option(sode_t h, const char* key, int64_t* value)
+{
+    if (!h || !key || !value)
+        return SODE_EINVAL;
+    if (std::strcmp(key, "precision") == 0)
+        *value = h->precision;
+    else if (std::strcmp(key, "method") == 0)
+        *value = h->method;
+    else if (std::strcmp(key, "observable") == 0)
+        *value = h->observable;
+    else if (std::strcmp(key, "kernel") == 0)
+        *value = h->kernel;
+    else if (std::strcmp(key, "shared_params") == 0)
+        *value = h->shared_params;
+    else
+        return SODE_EINVAL;
+    return SODE_OK;
+}
+
+int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, double t0,
+                      double dt, int64_t nsteps, int64_t stride, uint64_t seed,
+                      uint64_t orbit_offset, uint64_t step_offset, const uint32_t* orbit_ids,
+                      const uint64_t* orbit_seeds, void* out, void* stream)
+{
+    if (!h)
+        return SODE_EINVAL;
+    if (orbits < 0 || nsteps < 0 || stride < 1 || nsteps % stride != 0)
+        return SODE_EINVAL;
+    if (!std::isfinite(t0) || !std::isfinite(dt) || !(dt > 0.0))
+        return SODE_EINVAL;
+    if (step_offset > (1ull << 32) || (uint64_t)nsteps > (1ull << 32) - step_offset)
+        return SODE_EINVAL;
+    if (orbits > kMaxOrbits)
+        return SODE_EINVAL;
+    const int64_t nsave = nsteps / stride + 1;
+    const int64_t q = h->observable == sode::kKuramotoR ? 1 : h->n;
+    // Element count of out must fit comfortably in 64-bit byte offsets.
+    if (orbits > 0 && nsave > (INT64_MAX / 16) / orbits / q)
+        return SODE_EINVAL;
+    int kernel = 0;
+    const int choice = choose_kernel(h, &kernel);
+    if (choice != SODE_OK)
+        return choice;
+    if (orbits == 0)
+        return SODE_OK;
+    if (!X0 || !p || !out)
+        return SODE_EINVAL;
+
+    sode::Request r;
+    r.model = h->model;
+    r.n = h->n;
+    r.m = h->m;
+    r.d = h->d;
+    r.X0 = X0;
+    r.p = p;
+    r.p_per_orbit = h->shared_params ? 0 : 1;
+    r.orbits = orbits;
+    r.t0 = t0;
+    r.dt = dt;
+    r.nsteps = nsteps;
+    r.stride = stride;
+    r.nsave = nsave;
+    r.seed = seed;
+    r.orbit_offset = orbit_offset;
+    r.step_offset = step_offset;
+    r.orbit_ids = orbit_ids;
+    r.orbit_seeds = orbit_seeds;
+    r.method = h->method;
+    r.observable = h->observable;
+    r.out = out;
+    r.stream = static_cast<hipStream_t>(stream);
+
+    hipError_t e;
+    if (kernel == 2)
+        e = sode::launch_kuramoto_coupled_f32(r);
+    else if (h->precision == 64)
+        e = sode::launch_plain_f64(r);
+    else
+        e = sode::launch_plain_f32(r);
+    h->last_error = e;
+    h->last_stream = r.stream;
+    h->launched = true;
+    return status_of(e);
+}
+
+int sode_integrate(sode_t h, const void* X0, const void* p, int64_t orbits, double t0,
+                   double dt, int64_t nsteps, int64_t stride, uint64_t seed, void* out,
+                   void* stream)
+{
+    return sode_integrate_ex(h, X0, p, orbits, t0, dt, nsteps, stride, seed, 0, 0, nullptr,
+                             nullptr, out, stream);
+}
+
+int sode_sync(sode_t h)
+{
+    if (!h)
+        return SODE_EINVAL;
+    if (!h->launched)
+        return SODE_OK;
+    const hipError_t e = hipStreamSynchronize(h->last_stream);
+    if (e != hipSuccess)
+        return SODE_EDEVICE;
+    return status_of(h->last_error);
+}
+
+int sode_destroy(sode_t h)
+{
+    delete h;
+    return SODE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+"""The C ABI without a GPU: the library loads, exports every symbol that
+include/sode.h declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1908_03869_amd as sode
+from paper_1908_03869_amd import abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sode.h")
+
+# A non-null placeholder address; validation rejects every call below before
+# the pointer could be used.
+FAKE = 0x1000
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sode_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(abi.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    L = abi.load()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert abi.sode_version() >= 100
+
+
+def test_strerror_covers_every_status():
+    for st in (0, -1, -2, -3, -4, -5):
+        assert abi.sode_strerror(st) and abi.sode_strerror(st) != "unknown status"
+    assert abi.sode_strerror(-99) == "unknown status"
+
+
+@pytest.mark.parametrize("model,n,m,d,ok", [
+    ("kuramoto", 4, 4, 9, True), ("kuramoto", 4, 4, 8, False), ("kuramoto", 4, 3, 9, False),
+    ("ou", 3, 3, 3, True), ("ou", 3, 3, 2, False), ("gbm", 1, 1, 2, True),
+    ("fhn", 8, 4, 5, True), ("fhn", 7, 3, 5, False), ("rnn", 3, 3, 13, True),
+    ("rnn", 3, 3, 12, False), ("nonesuch", 4, 4, 9, False), ("kuramoto", 0, 0, 1, False),
+])
+def test_create_checks_model_dimensions(model, n, m, d, ok):
+    st, h = abi.sode_create(model, n, m, d)
+    assert (st == abi.SODE_OK) == ok
+    assert (h is not None) == ok
+    if h:
+        assert abi.sode_destroy(h) == 0
+
+
+def test_create_rejects_null_output():
+    L = abi.load()
+    assert L.sode_create(b"kuramoto", 4, 4, 9, None) == abi.SODE_EINVAL
+    assert L.sode_create(None, 4, 4, 9, ctypes.byref(ctypes.c_void_p())) == abi.SODE_EINVAL
+
+
+def test_options_round_trip_and_reject_unknown():
+    st, h = abi.sode_create("kuramoto", 64, 64, 129)
+    assert st == 0
+    try:
+        for key, val in (("precision", 64), ("method", 1), ("observable", 1), ("kernel", 2),
+                         ("shared_params", 1)):
+            assert abi.sode_set_option(h, key, val) == 0
+            assert abi.sode_get_option(h, key) == (0, val)
+        assert abi.sode_set_option(h, "precision", 16) == abi.SODE_EINVAL
+        assert abi.sode_set_option(h, "method", 2) == abi.SODE_EINVAL
+        assert abi.sode_set_option(h, "kernel", 7) == abi.SODE_EINVAL
+        assert abi.sode_set_option(h, "bogus", 1) == abi.SODE_EINVAL
+        assert abi.sode_get_option(h, "bogus")[0] == abi.SODE_EINVAL
+        assert abi.sode_get_option(h, "precision") == (0, 64)
+    finally:
+        abi.sode_destroy(h)
+    st, h = abi.sode_create("ou", 2, 2, 3)
+    assert abi.sode_set_option(h, "observable", 1) == abi.SODE_EINVAL  # r is Kuramoto only
+    abi.sode_destroy(h)
+
+
+def _call(h, **kw):
+    a = dict(X0=FAKE, p=FAKE, orbits=16, t0=0.0, dt=1e-3, nsteps=100, stride=10, seed=1,
+             orbit_offset=0, step_offset=0, orbit_ids=None, orbit_seeds=None, out=FAKE,
+             stream=None)
+    a.update(kw)
+    return abi.sode_integrate_ex(h, a["X0"], a["p"], a["orbits"], a["t0"], a["dt"], a["nsteps"],
+                                 a["stride"], a["seed"], a["orbit_offset"], a["step_offset"],
+                                 a["orbit_ids"], a["orbit_seeds"], a["out"], a["stream"])
+
+
+@pytest.mark.parametrize("bad", [
+    dict(orbits=-1), dict(nsteps=-5), dict(stride=0), dict(nsteps=105, stride=10),
+    dict(dt=0.0), dict(dt=-1e-3), dict(dt=float("nan")), dict(t0=float("inf")),
+    dict(X0=None), dict(p=None), dict(out=None), dict(step_offset=2**32 - 50),
+    dict(orbits=2**27 + 1),
+])
+def test_integrate_rejects_bad_arguments(bad):
+    st, h = abi.sode_create("kuramoto", 4, 4, 9)
+    try:
+        assert _call(h, **bad) == abi.SODE_EINVAL
+    finally:
+        abi.sode_destroy(h)
+
+
+def test_integrate_null_handle_and_zero_orbits():
+    assert _call(None) == abi.SODE_EINVAL
+    st, h = abi.sode_create("kuramoto", 4, 4, 9)
+    # Nothing to do: succeeds without touching the device or the pointers.
+    assert _call(h, orbits=0, X0=None, p=None, out=None) == abi.SODE_OK
+    assert abi.sode_sync(h) == abi.SODE_OK
+    abi.sode_destroy(h)
+
+
+def test_unsupported_kernel_requests():
+    st, h = abi.sode_create("kuramoto", 12, 12, 25)
+    abi.sode_set_option(h, "kernel", 2)  # coupled needs n in {16, 32, 64, 128}
+    assert _call(h) == abi.SODE_EUNSUPPORTED
+    abi.sode_destroy(h)
+    st, h = abi.sode_create("kuramoto", 64, 64, 129)
+    abi.sode_set_option(h, "kernel", 2)
+    abi.sode_set_option(h, "precision", 64)  # coupled is binary32 only
+    assert _call(h) == abi.SODE_EUNSUPPORTED
+    abi.sode_set_option(h, "precision", 32)
+    abi.sode_set_option(h, "method", 1)  # and Euler-Maruyama only
+    assert _call(h) == abi.SODE_EUNSUPPORTED
+    abi.sode_destroy(h)
+    st, h = abi.sode_create("ou", 200, 200, 3)  # beyond the plain kernel's 128 states
+    assert _call(h) == abi.SODE_EUNSUPPORTED
+    abi.sode_destroy(h)
+
+
+def test_python_layer_raises_on_error():
+    with pytest.raises(sode.SodeError):
+        sode.Integrator("kuramoto", 4, 4, 10)
+    it = sode.Integrator("kuramoto", 4, 4, 9, precision=64, method="rk4")
+    assert it.options["precision"] == 64 and it.options["method"] == 1
+    with pytest.raises(sode.SodeError):
+        it.set_option("precision", 8)
+    it.close()
+
+
+def test_destroy_accepts_null():
+    assert abi.sode_destroy(None) == 0
