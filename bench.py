@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--cpu-orbits", type=int, default=4,
                     help="orbits of the oracle sample (full 2x10^4 steps each)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device-to-device copy of this many MiB, so that "
+                         "HBM byte counters can be scaled against a kernel of known traffic")
     return ap.parse_args()
 
 
@@ -87,6 +90,12 @@ def main():
     import paper_1908_03869_amd as sode
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = workloads.kuramoto_grid()
     n, orbits, nsteps, stride = w["n"], w["X0"].shape[0], w["nsteps"], w["stride"]
     X0 = torch.tensor(w["X0"], dtype=torch.float32, device=dev)
