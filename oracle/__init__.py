@@ -5,8 +5,9 @@ library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares
 no code with the HIP path and never imports it.
 
-The arithmetic lives in ``sode_oracle.c`` (plain C, ``-O2 -ffp-contract=off``)
-and ``adjoint.py``; this module only marshals numpy arrays through ctypes.
+All arithmetic lives in ``sode_oracle.c`` (plain C, ``-O2 -ffp-contract=off``);
+this module only marshals numpy arrays through ctypes and shards orbits over
+threads.
 """
 from __future__ import annotations
 
@@ -70,6 +71,11 @@ def lib():
                ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
                ctypes.c_uint64, u32p, u64p, ctypes.c_int32, ctypes.c_int32, f64p])
         L.oracle_integrate.restype = ctypes.c_int
+        L.oracle_kuramoto_adjoint.argtypes = [
+            ctypes.c_int32, f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+            ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+            ctypes.c_uint64, ctypes.c_uint64, f64p, f64p, f64p, f64p]
+        L.oracle_kuramoto_adjoint.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -194,3 +200,66 @@ def integrate_parallel(model, n, m, d, X0, p, t0, dt, nsteps, stride, seed, *, t
     with ThreadPoolExecutor(max_workers=threads) as ex:
         parts = [r for r in ex.map(run, range(threads)) if r is not None]
     return np.concatenate(parts, axis=0)
+
+
+def kuramoto_adjoint(n: int, X0, p, t0: float, dt: float, nsteps: int, win_lo: int, win_hi: int,
+                     seed: int, *, dL_dR=None, orbit_offset: int = 0, step_offset: int = 0,
+                     per_orbit: bool = True):
+    """Window-averaged order parameter R[orbits] and its pathwise gradient.
+
+    Returns (R, grad[d], grad_per_orbit[orbits, d] or None); grad is
+    sum_o dL_dR[o] dR_o/dp (dL_dR defaults to ones)."""
+    d = 2 * n + 1
+    X0, X0p = _f64(X0)
+    X0 = X0.reshape(-1, n)
+    orbits = X0.shape[0]
+    p, pp = _f64(p)
+    p_per_orbit = p.ndim == 2
+    R = np.zeros(orbits)
+    grad = np.zeros(d)
+    gpo = np.zeros((orbits, d)) if per_orbit else None
+    f64p = ctypes.POINTER(ctypes.c_double)
+    w = None
+    wp = ctypes.POINTER(ctypes.c_double)()
+    if dL_dR is not None:
+        w = np.ascontiguousarray(dL_dR, dtype=np.float64)
+        wp = w.ctypes.data_as(f64p)
+    rc = lib().oracle_kuramoto_adjoint(
+        n, X0p, pp, int(p_per_orbit), orbits, t0, dt, nsteps, win_lo, win_hi, seed,
+        orbit_offset, step_offset, wp, R.ctypes.data_as(f64p),
+        gpo.ctypes.data_as(f64p) if gpo is not None else ctypes.POINTER(ctypes.c_double)(),
+        grad.ctypes.data_as(f64p))
+    if rc != 0:
+        raise ValueError(f"oracle_kuramoto_adjoint rejected its arguments (rc={rc})")
+    return R, grad, gpo
+
+
+def kuramoto_adjoint_parallel(n, X0, p, t0, dt, nsteps, win_lo, win_hi, seed, *, dL_dR=None,
+                              threads=8, orbit_offset=0, step_offset=0):
+    """``kuramoto_adjoint`` over disjoint orbit shards in threads; the
+    per-orbit gradients are then summed in orbit order, as one call would."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    X0 = np.ascontiguousarray(X0, dtype=np.float64).reshape(-1, n)
+    orbits = X0.shape[0]
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    per = p.ndim == 2
+    w = np.ones(orbits) if dL_dR is None else np.asarray(dL_dR, dtype=np.float64)
+    bounds = np.linspace(0, orbits, threads + 1).astype(int)
+
+    def run(i):
+        a, b = bounds[i], bounds[i + 1]
+        if a == b:
+            return None
+        return kuramoto_adjoint(n, X0[a:b], p[a:b] if per else p, t0, dt, nsteps, win_lo,
+                                win_hi, seed, dL_dR=w[a:b], orbit_offset=orbit_offset + a,
+                                step_offset=step_offset)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = [r for r in ex.map(run, range(threads)) if r is not None]
+    R = np.concatenate([r[0] for r in parts])
+    gpo = np.concatenate([r[2] for r in parts])
+    grad = np.zeros(2 * n + 1)
+    for row in gpo:
+        grad = grad + row
+    return R, grad, gpo

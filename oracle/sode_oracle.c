@@ -331,3 +331,124 @@ int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
     free(k1); free(k2); free(k3); free(k4); free(Y);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pathwise gradient of the time-averaged order parameter of Kuramoto orbits.
+ *
+ * Parameter fitting is the paper's motivating use (Sec. 1.2); the objective
+ * here is R = (1/W) sum_{k=lo..hi} r(X^k), W = hi - lo + 1, the order
+ * parameter of Eq. (7) averaged over a window of Euler-Maruyama iterates
+ * (Eq. 6).  With the noise held fixed (the same Philox stream), X^N is a
+ * deterministic function of p, and R's exact derivative is obtained by the
+ * discrete adjoint of the map X^{k+1} = Phi_k(X^k, p):
+ *     lambda^N = w_N grad r(X^N)
+ *     for k = N-1 .. 0:
+ *         g      += (d Phi_k / d p)^T lambda^{k+1}
+ *         lambda^k = (d Phi_k / d X)^T lambda^{k+1} + w_k grad r(X^k)
+ * with w_k = 1/W inside the window and 0 outside.  For the Kuramoto map
+ *     d Phi_i/d X_j = delta_ij + dt K/N [cos(X_j - X_i) - delta_ij sum_l cos(X_l - X_i)]
+ *     d Phi_i/d K   = dt/N sum_j sin(X_j - X_i)
+ *     d Phi_i/d omega_i = dt,   d Phi_i/d p_i = sqrt(dt) N_i
+ *     d r/d X_j = (S cos X_j - C sin X_j) / (N |Z|),  Z = C + iS = sum_j e^{i X_j}
+ * (0 when |Z| < 1e-30).  Every product is formed from these pairwise
+ * expressions; the full trajectory and its normals are stored.
+ *
+ *   R              [orbits]      objective of each orbit
+ *   grad_per_orbit [orbits][d]   dL/dR_o * dR_o/dp (may be NULL)
+ *   grad           [d]           sum over orbits in index order
+ * Returns 0, or -1 for an argument error.                                    */
+int oracle_kuramoto_adjoint(int32_t n, const double* X0, const double* p, int32_t p_per_orbit,
+                            int64_t orbits, double t0, double dt, int64_t nsteps,
+                            int64_t win_lo, int64_t win_hi, uint64_t seed,
+                            uint64_t orbit_offset, uint64_t step_offset,
+                            const double* dL_dR, double* R, double* grad_per_orbit, double* grad)
+{
+    const int32_t m = n, d = 2 * n + 1;
+    if (n <= 0 || orbits < 0 || nsteps < 0 || win_lo < 0 || win_hi < win_lo || win_hi > nsteps)
+        return -1;
+    (void)t0;
+    const double W = (double)(win_hi - win_lo + 1);
+    const double sqdt = sqrt(dt);
+    double* traj = (double*)malloc(sizeof(double) * (size_t)(nsteps + 1) * (size_t)n);
+    double* noise = (double*)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * (size_t)m);
+    double* f = (double*)malloc(sizeof(double) * (size_t)n);
+    double* gx = (double*)malloc(sizeof(double) * (size_t)n);
+    double* lam = (double*)malloc(sizeof(double) * (size_t)n);
+    double* mu = (double*)malloc(sizeof(double) * (size_t)n);
+    double* g = (double*)malloc(sizeof(double) * (size_t)d);
+    for (int32_t q = 0; q < d; ++q)
+        grad[q] = 0.0;
+
+    for (int64_t o = 0; o < orbits; ++o) {
+        const double* po = p + (p_per_orbit ? (size_t)o * (size_t)d : 0);
+        const double K = po[0];
+        const uint32_t id = (uint32_t)(orbit_offset + (uint64_t)o);
+        /* forward pass, storing every state and every normal */
+        memcpy(traj, X0 + (size_t)o * (size_t)n, sizeof(double) * (size_t)n);
+        for (int64_t k = 0; k < nsteps; ++k) {
+            const double* X = traj + (size_t)k * (size_t)n;
+            double* Xn = traj + (size_t)(k + 1) * (size_t)n;
+            double* xi = noise + (size_t)k * (size_t)m;
+            oracle_drift(M_KURAMOTO, n, m, d, t0 + (double)k * dt, X, po, f);
+            oracle_normals(seed, id, (uint32_t)(step_offset + (uint64_t)k), m, xi);
+            oracle_diffusion(M_KURAMOTO, n, m, d, t0 + (double)k * dt, X, po, xi, gx);
+            for (int32_t i = 0; i < n; ++i)
+                Xn[i] = X[i] + f[i] * dt + gx[i] * sqdt;
+        }
+        double Ro = 0.0;
+        for (int64_t k = win_lo; k <= win_hi; ++k)
+            Ro = Ro + oracle_order_parameter(n, traj + (size_t)k * (size_t)n);
+        Ro = Ro / W;
+        R[o] = Ro;
+
+        /* reverse pass */
+        for (int32_t q = 0; q < d; ++q)
+            g[q] = 0.0;
+        for (int32_t i = 0; i < n; ++i)
+            lam[i] = 0.0;
+        for (int64_t k = nsteps; k >= 0; --k) {
+            const double* X = traj + (size_t)k * (size_t)n;
+            if (k < nsteps) {
+                const double* xi = noise + (size_t)k * (size_t)m;
+                /* parameter sensitivities of Phi_k against lambda^{k+1} */
+                for (int32_t i = 0; i < n; ++i) {
+                    double s = 0.0;
+                    for (int32_t j = 0; j < n; ++j)
+                        s = s + sin(X[j] - X[i]);
+                    g[0] = g[0] + lam[i] * (dt / (double)n) * s;
+                    g[1 + i] = g[1 + i] + lam[i] * dt;
+                    g[1 + n + i] = g[1 + n + i] + lam[i] * sqdt * xi[i];
+                }
+                /* lambda^k = (d Phi_k / d X)^T lambda^{k+1} */
+                for (int32_t j = 0; j < n; ++j) {
+                    double a = 0.0, b = 0.0;
+                    for (int32_t i = 0; i < n; ++i) {
+                        a = a + lam[i] * cos(X[j] - X[i]);
+                        b = b + cos(X[i] - X[j]);
+                    }
+                    mu[j] = lam[j] + dt * (K / (double)n) * (a - lam[j] * b);
+                }
+                memcpy(lam, mu, sizeof(double) * (size_t)n);
+            }
+            if (k >= win_lo && k <= win_hi) {
+                double c = 0.0, s = 0.0;
+                for (int32_t j = 0; j < n; ++j) {
+                    c = c + cos(X[j]);
+                    s = s + sin(X[j]);
+                }
+                const double z = sqrt(c * c + s * s);
+                if (z >= 1e-30)
+                    for (int32_t j = 0; j < n; ++j)
+                        lam[j] = lam[j] + (s * cos(X[j]) - c * sin(X[j])) / ((double)n * z) / W;
+            }
+        }
+        const double wgt = dL_dR ? dL_dR[o] : 1.0;
+        for (int32_t q = 0; q < d; ++q) {
+            if (grad_per_orbit)
+                grad_per_orbit[(size_t)o * (size_t)d + q] = wgt * g[q];
+            grad[q] = grad[q] + wgt * g[q];
+        }
+    }
+    free(traj); free(noise); free(f); free(gx); free(lam); free(mu); free(g);
+    return 0;
+}

@@ -361,3 +361,63 @@ def test_e4_coherence_either_side_of_critical_coupling(oracle_lib):
             assert r_end < case["r_mean_at_end_below"], r_end
         else:
             assert r_end > case["r_mean_at_end_above"], r_end
+
+
+# --------------------------------------------------------------------------- adjoint
+def _window_R(oracle_lib, n, X0, p, dt, nsteps, lo, hi, seed):
+    out = oracle_lib.integrate("kuramoto", n, n, 2 * n + 1, X0, p, 0.0, dt, nsteps, 1, seed,
+                               observable="kuramoto_r")
+    return out[:, lo:hi + 1, 0].mean(axis=1)
+
+
+def test_adjoint_matches_central_differences(oracle_lib):
+    """The discrete adjoint equals central finite differences of the FP64
+    forward map (same noise) for every parameter of every orbit."""
+    n, dt, nsteps, lo, hi, seed = 4, 1e-2, 300, 150, 300, 31
+    rng = np.random.default_rng(21)
+    X0 = rng.uniform(0, 2 * math.pi, (3, n))
+    p = workloads.kuramoto_params(rng.uniform(0.5, 3, 3), rng.standard_normal((3, n)),
+                                  rng.uniform(0.05, 0.4, (3, n)))
+    R, grad, gpo = oracle_lib.kuramoto_adjoint(n, X0, p, 0.0, dt, nsteps, lo, hi, seed)
+    np.testing.assert_allclose(R, _window_R(oracle_lib, n, X0, p, dt, nsteps, lo, hi, seed),
+                               rtol=0, atol=1e-14)
+    h = 1e-6
+    fd = np.zeros_like(gpo)
+    for q in range(2 * n + 1):
+        pp, pm = p.copy(), p.copy()
+        pp[:, q] += h
+        pm[:, q] -= h
+        fd[:, q] = (_window_R(oracle_lib, n, X0, pp, dt, nsteps, lo, hi, seed)
+                    - _window_R(oracle_lib, n, X0, pm, dt, nsteps, lo, hi, seed)) / (2 * h)
+    np.testing.assert_allclose(gpo, fd, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(grad, gpo.sum(axis=0), rtol=1e-13)
+
+
+def test_adjoint_uncoupled_closed_form(oracle_lib):
+    """K = 0: the oscillators move independently, dX_i^k/d omega_i = k dt,
+    dX_i^k/d p_i = sqrt(dt) sum_{l<k} N_{l,i} and dX_i^k/dK =
+    dt/N sum_{l<k} sum_j sin(X_j^l - X_i^l), so dR/dp is a forward sum of
+    dr/dX_i = (S cos X_i - C sin X_i)/(N |Z|) along the trajectory."""
+    n, dt, nsteps, lo, hi, seed = 5, 2e-2, 200, 100, 200, 8
+    rng = np.random.default_rng(5)
+    X0 = rng.uniform(0, 2 * math.pi, (1, n))
+    p = workloads.kuramoto_params([0.0], rng.standard_normal((1, n)), rng.uniform(0.1, 0.5, (1, n)))
+    R, grad, _ = oracle_lib.kuramoto_adjoint(n, X0, p[0], 0.0, dt, nsteps, lo, hi, seed)
+    traj = oracle_lib.integrate("kuramoto", n, n, 2 * n + 1, X0, p, 0.0, dt, nsteps, 1, seed)[0]
+    xi = np.stack([oracle_lib.normals(seed, 0, k, n) for k in range(nsteps)])
+    W = hi - lo + 1
+    want = np.zeros(2 * n + 1)
+    dXdK = np.zeros(n)
+    noise_sum = np.zeros(n)
+    for k in range(nsteps + 1):
+        X = traj[k]
+        if lo <= k <= hi:
+            C, S = np.cos(X).sum(), np.sin(X).sum()
+            drdx = (S * np.cos(X) - C * np.sin(X)) / (n * math.hypot(C, S))
+            want[0] += drdx @ dXdK / W
+            want[1:n + 1] += drdx * k * dt / W
+            want[n + 1:] += drdx * math.sqrt(dt) * noise_sum / W
+        if k < nsteps:
+            dXdK += dt / n * np.array([np.sin(X - X[i]).sum() for i in range(n)])
+            noise_sum += xi[k]
+    np.testing.assert_allclose(grad, want, rtol=1e-10, atol=1e-13)
