@@ -37,7 +37,7 @@ VALU_LANE_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 SLOTS = {"valu": 1.0, "trans": 4.0, "imul": 2.0}
 
 
-def algorithmic_slots_per_orbit_step(n: int) -> dict:
+def algorithmic_slots_per_orbit_step(n: int, compensated: bool = True) -> dict:
     """Minimal work of one Euler-Maruyama step of one n-oscillator orbit with
     pairwise sine coupling (each unordered pair once), Philox-4x32-10 noise
     and Box-Muller normals; counted from the formulation, not the ISA."""
@@ -47,8 +47,10 @@ def algorithmic_slots_per_orbit_step(n: int) -> dict:
     counts = {
         # per pair: one difference, one sine, two accumulations
         "valu": pairs * 3
-        # per oscillator: scale to revolutions, two FMAs, one add, wrap (3)
-        + n * 7
+        # per oscillator: scale to revolutions, two FMAs for the increment,
+        # the state update (a six-op two-sum when compensated, else one
+        # add) and the 2 pi wrap (scale, round, two FMAs)
+        + n * (3 + (6 if compensated else 1) + 4)
         # per Box-Muller pair: two int->float conversions, two scalings,
         # one radius scaling, two products
         + bm_pairs * 7
@@ -59,6 +61,42 @@ def algorithmic_slots_per_orbit_step(n: int) -> dict:
     }
     counts["slots"] = sum(counts[k] * SLOTS[k] for k in SLOTS)
     return counts
+
+
+def adjoint_leg(sode, torch, workloads, dev, reps: int = 3) -> dict:
+    """Forward (with checkpoints) and backward (adjoint) times of the n = 32
+    gradient workload: 4096 orbits sharing (omega, K, sigma), 10^4 steps,
+    checkpoints every 100, R = mean r over steps 5000..10000."""
+    w = workloads.kuramoto_adjoint()
+    n = w["n"]
+    X0 = torch.tensor(w["X0"], dtype=torch.float32, device=dev)
+    p = torch.tensor(w["p"], dtype=torch.float32, device=dev)
+    it = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, shared_params=1)
+    args = (0.0, w["dt"], w["nsteps"], w["ckpt_every"], w["win_lo"], w["win_hi"], w["seed"])
+    stream = torch.cuda.current_stream()
+    fwd, bwd = [], []
+    for rep in range(reps + 1):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        ckpt, R = it.forward_ckpt(X0, p, *args)
+        e1.record(stream)
+        dLdR = 2.0 * (R - w["target"]) / R.numel()
+        e1b = torch.cuda.Event(enable_timing=True)
+        e1b.record(stream)
+        grad, _ = it.adjoint(p, ckpt, *args, dL_dR=dLdR)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if rep > 0:
+            fwd.append(e0.elapsed_time(e1))
+            bwd.append(e1b.elapsed_time(e2))
+    f, b = float(np.median(fwd)), float(np.median(bwd))
+    orbits = X0.shape[0]
+    return {"workload": "kuramoto_adjoint_n32", "orbits": orbits, "nsteps": w["nsteps"],
+            "forward_ms": f, "backward_ms": b, "ratio_backward_over_forward": b / f,
+            "ratio_total_over_forward": (f + b) / f,
+            "forward_orbit_steps_per_s": orbits * w["nsteps"] / (f * 1e-3),
+            "loss": float(((R - w["target"]) ** 2).mean()),
+            "grad_norm": float(grad.norm())}
 
 
 def parse():
@@ -145,13 +183,18 @@ def main():
     plain_ms = b0.elapsed_time(b1)
     plain_rate = orbits * bsteps / (plain_ms * 1e-3)
 
+    adj = adjoint_leg(sode, torch, workloads, dev)
+
     cpu = None
     err = None
     if not args.no_cpu:
         import oracle
         rows = w["diagonal"][np.linspace(0, 255, args.cpu_orbits).astype(int)]
         c0 = time.perf_counter()
-        ref = oracle.integrate("kuramoto", n, n, 2 * n + 1, w["X0"][rows], w["p"][rows], 0.0,
+        # The oracle gets the float32-rounded inputs the kernel received.
+        X32 = w["X0"][rows].astype(np.float32).astype(np.float64)
+        p32 = w["p"][rows].astype(np.float32).astype(np.float64)
+        ref = oracle.integrate("kuramoto", n, n, 2 * n + 1, X32, p32, 0.0,
                                w["dt"], nsteps, stride, w["seed"], orbit_ids=rows,
                                observable="kuramoto_r")
         cpu_s = time.perf_counter() - c0
@@ -187,6 +230,7 @@ def main():
         "plain_fp64": {"value": plain_rate, "unit": "orbit*steps/s", "nsteps": bsteps,
                        "speedup_of_value": value / plain_rate},
         "error": {"max_abs_dr_final": err, "tolerance": 1e-4},
+        "adjoint": adj,
     }
     print(json.dumps(line))
 

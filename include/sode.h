@@ -53,6 +53,13 @@ enum sode_status {
  *                    m = n, d = 3, p = (a, mu, s).
  *        "gbm":      geometric Brownian motion, dX_i = mu X_i dt + s X_i dW_i;
  *                    m = n, d = 2, p = (mu, s).
+ *        "fhn":      FitzHugh-Nagumo chain of N = n/2 units, state
+ *                    (v_1..v_N, w_1..w_N), dv_i = [v_i - v_i^3/3 - w_i +
+ *                    D (v_{i-1} - 2 v_i + v_{i+1})] dt + sigma dW_i,
+ *                    dw_i = eps (v_i + a - b w_i) dt, no-flux ends;
+ *                    m = N, d = 5, p = (a, b, eps, D, sigma).
+ *        "rnn":      dense random network, dX = (-X + W tanh X + b) dt +
+ *                    sigma dW; m = n, d = n^2 + n + 1, p = (W row-major, b, sigma).
  * n, m, d must match the model, else SODE_EINVAL.  On success *out receives
  * a new handle with default options (precision 32, method EM, observable
  * "state", kernel auto, per-orbit parameters).  No HIP call is made.
@@ -76,6 +83,13 @@ int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out)
  *                  orbit exchange phases through DPP row rotations).
  *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
  *                  used by every orbit.
+ *   "compensated"  binary32 Kuramoto kernels (coupled, forward_ckpt,
+ *                  adjoint): 1 (default) carries each phase as hi + lo and
+ *                  adds every increment with an error-free two-sum, so the
+ *                  trajectory stays within ~1e-9 rad of exact arithmetic
+ *                  (saved states hold hi; resuming from them restarts lo at
+ *                  0); 0 keeps a single binary32 phase (saved states resume
+ *                  bit-exactly).
  * Unknown keys or values give SODE_EINVAL and leave the handle unchanged.
  */
 int sode_set_option(sode_t h, const char* key, int64_t value);
@@ -126,6 +140,47 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
                       double dt, int64_t nsteps, int64_t stride, uint64_t seed,
                       uint64_t orbit_offset, uint64_t step_offset, const uint32_t* orbit_ids,
                       const uint64_t* orbit_seeds, void* out, void* stream);
+
+/*
+ * sode_forward_ckpt - Euler-Maruyama integration of Kuramoto orbits that
+ * keeps what a pathwise gradient needs: every `ckpt_every`-th state and the
+ * window-averaged order parameter
+ *     R_o = (1/W) sum_{k = win_lo .. win_hi} r(X_o^k),  W = win_hi - win_lo + 1,
+ * with r of Eq. (7) (Sec. 2.3.1), accumulated in binary64.  Parameter
+ * fitting over many orbits is the use the paper builds toward (Sec. 1.2).
+ *
+ * Handle: model "kuramoto", precision 32, method EM, n in {16, 32, 64, 128}
+ * (else SODE_EUNSUPPORTED).  Noise addressing as sode_integrate_ex with
+ * orbit ids orbit_offset + o and the single `seed`.  Step indices k are
+ * local to the call (k = 0 is X0); 0 <= win_lo <= win_hi <= nsteps,
+ * nsteps % ckpt_every == 0, else SODE_EINVAL.
+ *   ckpt  [orbits][nsteps/ckpt_every + 1][n] float, ckpt[o][c] = X^{c*ckpt_every}
+ *   R     [orbits] double
+ */
+int sode_forward_ckpt(sode_t h, const void* X0, const void* p, int64_t orbits, double t0,
+                      double dt, int64_t nsteps, int64_t ckpt_every, int64_t win_lo,
+                      int64_t win_hi, uint64_t seed, uint64_t orbit_offset, uint64_t step_offset,
+                      void* ckpt, double* R, void* stream);
+
+/*
+ * sode_adjoint - gradient of sum_o dL_dR[o] R_o with respect to p by the
+ * discrete adjoint of the Euler-Maruyama map, for checkpoints written by
+ * sode_forward_ckpt with the same arguments.  The noise is regenerated from
+ * the Philox counter (common random numbers), segments between checkpoints
+ * are recomputed bit-identically, and gradients are accumulated in binary64.
+ *
+ *   dL_dR            [orbits] double, or NULL for all ones.
+ *   grad_p           [d] double, sum over orbits in a fixed order (may be
+ *                    NULL if grad_p_per_orbit is given).
+ *   grad_p_per_orbit [orbits][d] double, dL_dR[o] * dR_o/dp, or NULL.
+ * The library keeps a device scratch area of orbits * ckpt_every * n floats
+ * (plus orbits * d doubles when grad_p_per_orbit is NULL) in the handle;
+ * growing it may allocate (SODE_ENOMEM on failure).
+ */
+int sode_adjoint(sode_t h, const void* p, int64_t orbits, double t0, double dt, int64_t nsteps,
+                 int64_t ckpt_every, int64_t win_lo, int64_t win_hi, uint64_t seed,
+                 uint64_t orbit_offset, uint64_t step_offset, const void* ckpt,
+                 const double* dL_dR, double* grad_p, double* grad_p_per_orbit, void* stream);
 
 /*
  * sode_sync - wait for the handle's last launch and report device errors.

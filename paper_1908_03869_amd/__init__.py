@@ -10,7 +10,7 @@ from __future__ import annotations
 from . import abi
 from .abi import SodeError, check
 
-__all__ = ["abi", "Integrator", "SodeError", "check", "OPTION_VALUES"]
+__all__ = ["abi", "Integrator", "SodeError", "check", "OPTION_VALUES", "KuramotoWindowR"]
 
 OPTION_VALUES = {
     "method": {"em": 0, "rk4": 1},
@@ -32,7 +32,7 @@ class Integrator:
         self.handle = h
         self.model, self.n, self.m, self.d = model, n, m, d
         self.options = {"precision": 32, "method": 0, "observable": 0, "kernel": 0,
-                        "shared_params": 0}
+                        "shared_params": 0, "compensated": 1}
         for k, v in options.items():
             self.set_option(k, v)
 
@@ -73,6 +73,57 @@ class Integrator:
         check(st, "sode_integrate_ex")
         return out
 
+    def _shared(self, p) -> None:
+        want = 1 if p.dim() == 1 else 0
+        if self.options["shared_params"] != want:
+            self.set_option("shared_params", want)
+
+    def forward_ckpt(self, X0, p, t0: float, dt: float, nsteps: int, ckpt_every: int,
+                     win_lo: int, win_hi: int, seed: int, *, orbit_offset: int = 0,
+                     step_offset: int = 0, stream=None):
+        """sode_forward_ckpt: returns (ckpt[orbits, nsteps/ckpt_every+1, n] float32,
+        R[orbits] float64)."""
+        import torch
+        self._shared(p)
+        orbits = X0.shape[0]
+        for name, t in (("X0", X0), ("p", p)):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
+        nck = nsteps // ckpt_every + 1 if ckpt_every > 0 else 0
+        ckpt = torch.empty((orbits, max(nck, 0), self.n), dtype=torch.float32, device=X0.device)
+        R = torch.empty(orbits, dtype=torch.float64, device=X0.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(X0.device).cuda_stream
+        st = abi.sode_forward_ckpt(self.handle, X0.data_ptr(), p.data_ptr(), orbits, t0, dt,
+                                   nsteps, ckpt_every, win_lo, win_hi, seed, orbit_offset,
+                                   step_offset, ckpt.data_ptr(), R.data_ptr(), stream)
+        check(st, "sode_forward_ckpt")
+        return ckpt, R
+
+    def adjoint(self, p, ckpt, t0: float, dt: float, nsteps: int, ckpt_every: int, win_lo: int,
+                win_hi: int, seed: int, dL_dR=None, *, per_orbit: bool = False,
+                orbit_offset: int = 0, step_offset: int = 0, stream=None):
+        """sode_adjoint: returns (grad[d] float64, rows[orbits, d] float64 or None)."""
+        import torch
+        self._shared(p)
+        orbits = ckpt.shape[0]
+        dev = ckpt.device
+        if p.dtype != torch.float32 or not p.is_contiguous() or not ckpt.is_contiguous():
+            raise ValueError("p and ckpt must be contiguous float32 GPU tensors")
+        if dL_dR is not None and (dL_dR.dtype != torch.float64 or not dL_dR.is_contiguous()
+                                  or dL_dR.numel() != orbits):
+            raise ValueError("dL_dR must be a contiguous float64 tensor with one entry per orbit")
+        grad = torch.empty(self.d, dtype=torch.float64, device=dev)
+        rows = torch.empty((orbits, self.d), dtype=torch.float64, device=dev) if per_orbit else None
+        if stream is None:
+            stream = torch.cuda.current_stream(dev).cuda_stream
+        st = abi.sode_adjoint(self.handle, p.data_ptr(), orbits, t0, dt, nsteps, ckpt_every,
+                              win_lo, win_hi, seed, orbit_offset, step_offset, ckpt.data_ptr(),
+                              None if dL_dR is None else dL_dR.data_ptr(), grad.data_ptr(),
+                              None if rows is None else rows.data_ptr(), stream)
+        check(st, "sode_adjoint")
+        return grad, rows
+
     def sync(self) -> None:
         check(abi.sode_sync(self.handle), "sode_sync")
 
@@ -86,3 +137,47 @@ class Integrator:
             self.close()
         except Exception:
             pass
+
+
+def _window_r_function():
+    import torch
+
+    class KuramotoWindowR(torch.autograd.Function):
+        """R[orbits] = window-averaged order parameter of Kuramoto orbits as a
+        differentiable function of the parameters p ([d] shared or [orbits, d]).
+
+        forward:  sode_forward_ckpt (checkpoints kept for the backward pass)
+        backward: sode_adjoint with dL_dR = grad_R (common random numbers)."""
+
+        @staticmethod
+        def forward(ctx, p, X0, integrator, t0, dt, nsteps, ckpt_every, win_lo, win_hi, seed):
+            ckpt, R = integrator.forward_ckpt(X0, p.detach().contiguous(), t0, dt, nsteps,
+                                              ckpt_every, win_lo, win_hi, seed)
+            ctx.integrator = integrator
+            ctx.args = (t0, dt, nsteps, ckpt_every, win_lo, win_hi, seed)
+            ctx.save_for_backward(p, ckpt)
+            return R
+
+        @staticmethod
+        def backward(ctx, grad_R):
+            p, ckpt = ctx.saved_tensors
+            per = p.dim() == 2
+            grad, rows = ctx.integrator.adjoint(p.detach().contiguous(), ckpt, *ctx.args,
+                                                dL_dR=grad_R.double().contiguous(),
+                                                per_orbit=per)
+            g = rows if per else grad
+            return (g.to(p.dtype),) + (None,) * 9
+
+    return KuramotoWindowR
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _Lazy._cls is None:
+            _Lazy._cls = _window_r_function()
+        return getattr(_Lazy._cls, name)
+
+
+KuramotoWindowR = _Lazy()

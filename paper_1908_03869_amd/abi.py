@@ -23,7 +23,8 @@ SODE_ENONFINITE = -5
 # Every symbol include/sode.h declares.
 EXPORTS = (
     "sode_create", "sode_set_option", "sode_get_option", "sode_integrate",
-    "sode_integrate_ex", "sode_sync", "sode_destroy", "sode_strerror", "sode_version",
+    "sode_integrate_ex", "sode_forward_ckpt", "sode_adjoint", "sode_sync", "sode_destroy",
+    "sode_strerror", "sode_version",
 )
 
 _lib = None
@@ -58,6 +59,12 @@ def load() -> ctypes.CDLL:
     L.sode_integrate_ex.argtypes = [vp, vp, vp, i64, f64, f64, i64, i64, u64, u64, u64, vp, vp,
                                     vp, vp]
     L.sode_integrate_ex.restype = ctypes.c_int
+    L.sode_forward_ckpt.argtypes = [vp, vp, vp, i64, f64, f64, i64, i64, i64, i64, u64, u64, u64,
+                                    vp, vp, vp]
+    L.sode_forward_ckpt.restype = ctypes.c_int
+    L.sode_adjoint.argtypes = [vp, vp, i64, f64, f64, i64, i64, i64, i64, u64, u64, u64, vp, vp,
+                               vp, vp, vp]
+    L.sode_adjoint.restype = ctypes.c_int
     L.sode_sync.argtypes = [vp]
     L.sode_sync.restype = ctypes.c_int
     L.sode_destroy.argtypes = [vp]
@@ -96,6 +103,19 @@ def sode_integrate_ex(h, X0, p, orbits, t0, dt, nsteps, stride, seed, orbit_offs
     return load().sode_integrate_ex(h, X0, p, orbits, t0, dt, nsteps, stride, seed,
                                     orbit_offset, step_offset, orbit_ids, orbit_seeds, out,
                                     stream)
+
+
+def sode_forward_ckpt(h, X0, p, orbits, t0, dt, nsteps, ckpt_every, win_lo, win_hi, seed,
+                      orbit_offset, step_offset, ckpt, R, stream) -> int:
+    return load().sode_forward_ckpt(h, X0, p, orbits, t0, dt, nsteps, ckpt_every, win_lo, win_hi,
+                                    seed, orbit_offset, step_offset, ckpt, R, stream)
+
+
+def sode_adjoint(h, p, orbits, t0, dt, nsteps, ckpt_every, win_lo, win_hi, seed, orbit_offset,
+                 step_offset, ckpt, dL_dR, grad_p, grad_p_per_orbit, stream) -> int:
+    return load().sode_adjoint(h, p, orbits, t0, dt, nsteps, ckpt_every, win_lo, win_hi, seed,
+                               orbit_offset, step_offset, ckpt, dL_dR, grad_p, grad_p_per_orbit,
+                               stream)
 
 
 def sode_sync(h) -> int:

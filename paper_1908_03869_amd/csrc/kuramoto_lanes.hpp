@@ -1,0 +1,257 @@
+// kuramoto_lanes.hpp - device building blocks shared by the binary32
+// Kuramoto kernels that map one orbit to a 16-lane DPP row (integration,
+// checkpointed forward pass and adjoint).  All of them step through
+// em_step(), so a recomputed segment reproduces the forward pass bit for bit.
+//
+// Lane l of a row owns the P = N/16 consecutive oscillators P*l .. P*l+P-1.
+// The state is kept in radians, wrapped to [-pi, pi] after every step with a
+// two-constant 2 pi reduction (no rounding when no wrap occurs).  With
+// compensation off the saved phases are the state itself, so a saved state
+// fed back in resumes bit-exactly.  With compensation on each phase is an
+// unevaluated sum hi + lo: the rounding error of every update is carried in
+// lo (two-sum), which keeps the binary32 trajectory within ~1e-9 rad of the
+// exact-arithmetic one instead of random-walking by ~1e-7 rad per step;
+// saves and checkpoints hold hi.  Once per step each phase is scaled to revolutions, the
+// argument unit of the hardware v_sin_f32, which then evaluates
+// sin(theta_j - theta_i) straight from the difference of two scaled phases.
+//
+// Coupling sum S_i = sum_j sin(theta_j - theta_i).  The paper's loop (Fig. 5)
+// evaluates all N^2 sines; here every unordered pair {i, j} is evaluated
+// once and used twice, since sin(theta_i - theta_j) = -sin(theta_j - theta_i)
+// exactly in IEEE arithmetic (the difference and the sine are both odd
+// under negation) and the j = i term is sin(0) = 0.  Pairs inside a lane
+// use registers; a pair between lane l and lane l' = l (+/-) k (k = 1..7)
+// is evaluated by one of the two lanes, which reads the partner's phases
+// with a DPP row rotation and returns the negated partial sums with the
+// inverse rotation; for k = 8 both lanes evaluate their own side.  Per
+// orbit-step this is N(N-1)/2 + N^2/32 sines instead of N^2.
+//
+// Noise: lane l needs normals P*l .. P*l+P-1, i.e. Philox blocks
+// floor(P*l/4) .. floor((P*l+P-1)/4) of its orbit (Sec. 2.1.2).
+#pragma once
+
+#include "noise.hpp"
+
+// Every product and sum below rounds as written; fused multiply-adds appear
+// only where spelled out, so the arithmetic does not depend on the kernel the
+// code is inlined into.
+#pragma clang fp contract(off)
+
+namespace sode {
+namespace kuramoto {
+
+constexpr float kInvTwoPi = 0.159154943091895335768883763373f;
+// 2 pi as its binary32 value plus the binary32 remainder.  The reduction
+// theta - k head - k tail with fused multiply-adds leaves theta untouched
+// when k = 0 (no wrap this step) and otherwise rounds twice.
+constexpr float kTwoPiHead = 6.28318548202514648437500f;
+constexpr float kTwoPiTail = -1.74845553146951715461e-07f;
+constexpr float kPiF = 3.14159274101257324219f;  // binary32 pi, just above pi
+
+// Value of `v` held by another lane of the same 16-lane row, selected by a
+// DPP row rotation (control 0x120 + r, r = 1..15).
+template <int R>
+__device__ __forceinline__ float row_rotate(float v)
+{
+    static_assert(R >= 1 && R <= 15, "row rotation amount");
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x120 + R, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+// theta reduced to [-pi, pi]: theta - 2 pi rint(theta / 2 pi).
+__device__ __forceinline__ float wrap_rad(float x)
+{
+    const float k = __builtin_rintf(x * kInvTwoPi);
+    x = __builtin_fmaf(-k, kTwoPiHead, x);
+    return __builtin_fmaf(-k, kTwoPiTail, x);
+}
+
+// Pairs between this lane and the lane K rotations away (K = 1..7).
+template <int P, int K>
+__device__ __forceinline__ void couple_across(const float (&phi)[P], float (&acc)[P])
+{
+    float other[P], back[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+        other[b] = row_rotate<16 - K>(phi[b]);
+        back[b] = 0.0f;
+    }
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+            const float s = sin_rev(other[b] - phi[a]);
+            acc[a] += s;
+            back[b] += s;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < P; ++b)
+        acc[b] -= row_rotate<K>(back[b]);
+}
+
+template <int P, int K>
+__device__ __forceinline__ void couple_rotations(const float (&phi)[P], float (&acc)[P])
+{
+    if constexpr (K <= 7) {
+        couple_across<P, K>(phi, acc);
+        couple_rotations<P, K + 1>(phi, acc);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void coupling_sums(const float (&phi)[P], float (&acc)[P])
+{
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+        acc[a] = 0.0f;
+    // Pairs inside the lane.
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+#pragma unroll
+        for (int b = a + 1; b < P; ++b) {
+            const float s = sin_rev(phi[b] - phi[a]);
+            acc[a] += s;
+            acc[b] -= s;
+        }
+    }
+    couple_rotations<P, 1>(phi, acc);
+    // Opposite lane (rotation by 8 is its own inverse): each side adds its own.
+    float other[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b)
+        other[b] = row_rotate<8>(phi[b]);
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+#pragma unroll
+        for (int b = 0; b < P; ++b)
+            acc[a] += sin_rev(other[b] - phi[a]);
+    }
+}
+
+// Normals P*l .. P*l+P-1 of one orbit at global step k.
+template <int P>
+__device__ __forceinline__ void lane_normals(const Stream& st, uint32_t k, int l, float (&xi)[P])
+{
+    if constexpr (P % 4 == 0) {
+#pragma unroll
+        for (int g = 0; g < P / 4; ++g) {
+            const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)(l * (P / 4) + g), 0u, st.key_lo, st.key_hi);
+            box_muller_f32(w.w0, w.w1, xi[4 * g + 0], xi[4 * g + 1]);
+            box_muller_f32(w.w2, w.w3, xi[4 * g + 2], xi[4 * g + 3]);
+        }
+    } else if constexpr (P == 2) {
+        const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)(l >> 1), 0u, st.key_lo, st.key_hi);
+        const bool upper = (l & 1) != 0;
+        box_muller_f32(upper ? w.w2 : w.w0, upper ? w.w3 : w.w1, xi[0], xi[1]);
+    } else {
+        static_assert(P == 1, "oscillators per lane");
+        const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)(l >> 2), 0u, st.key_lo, st.key_hi);
+        const bool upper = (l & 2) != 0;
+        float zc, zs;
+        box_muller_f32(upper ? w.w2 : w.w0, upper ? w.w3 : w.w1, zc, zs);
+        xi[0] = (l & 1) ? zs : zc;
+    }
+}
+
+// Sum over the 16 lanes of a row; every lane receives the total.
+__device__ __forceinline__ float row_sum(float v)
+{
+    v += row_rotate<8>(v);
+    v += row_rotate<4>(v);
+    v += row_rotate<2>(v);
+    v += row_rotate<1>(v);
+    return v;
+}
+
+// Per-lane constants of the Euler-Maruyama map in radians: omega_i dt,
+// p_i sqrt(dt) and K dt / N.
+template <int P>
+struct LaneCoefficients {
+    float drift0[P];
+    float noise_scale[P];
+    float kc;
+};
+
+template <int P>
+__device__ __forceinline__ LaneCoefficients<P> lane_coefficients(const float* __restrict__ p, int l,
+                                                                 float dt, float sqdt, float dt_over_n)
+{
+    constexpr int N = 16 * P;
+    LaneCoefficients<P> c;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int osc = P * l + i;
+        c.drift0[i] = p[1 + osc] * dt;
+        c.noise_scale[i] = p[1 + N + osc] * sqdt;
+    }
+    c.kc = p[0] * dt_over_n;
+    return c;
+}
+
+// Phase of an initial or checkpointed state.  A value already in range is
+// taken as is, so a saved state passed back in continues bit-exactly.
+__device__ __forceinline__ float load_phase(float x) { return __builtin_fabsf(x) <= kPiF ? x : wrap_rad(x); }
+
+// One Euler-Maruyama step (Eq. 6) of the lane's P oscillators at global
+// step k: theta += omega dt + (K/N) S dt + p sqrt(dt) xi, then wrap.
+// COMP: th is the leading part of hi + lo and tl the trailing part; the
+// increment and the old trailing part are added with an error-free two-sum,
+// and a wrap moves the tail of 2 pi into tl.
+template <int P, bool COMP>
+__device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const LaneCoefficients<P>& c,
+                                        const Stream& st, uint32_t k, int l)
+{
+    float phi[P], acc[P], xi[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        phi[i] = th[i] * kInvTwoPi;
+    coupling_sums<P>(phi, acc);
+    lane_normals<P>(st, k, l, xi);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const float inc = __builtin_fmaf(c.noise_scale[i], xi[i], __builtin_fmaf(c.kc, acc[i], c.drift0[i]));
+        if constexpr (COMP) {
+            const float y = inc + tl[i];
+            const float s = th[i] + y;
+            const float yv = s - th[i];
+            const float err = (th[i] - (s - yv)) + (y - yv);
+            const float kw = __builtin_rintf(s * kInvTwoPi);
+            th[i] = __builtin_fmaf(-kw, kTwoPiHead, s);
+            tl[i] = __builtin_fmaf(-kw, kTwoPiTail, err);
+        } else {
+            th[i] = wrap_rad(th[i] + inc);
+        }
+    }
+}
+
+// Row sums of cos(theta) and sin(theta) (every lane of the row gets them).
+template <int P>
+__device__ __forceinline__ void phase_sums(const float (&th)[P], float (&cs)[P], float (&sn)[P], float& C, float& S)
+{
+    float c = 0.0f, s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const float rev = th[q] * kInvTwoPi;
+        cs[q] = cos_rev(rev);
+        sn[q] = sin_rev(rev);
+        c += cs[q];
+        s += sn[q];
+    }
+    C = row_sum(c);
+    S = row_sum(s);
+}
+
+// Order parameter of Eq. (7): r = |sum_j e^{i theta_j}| / N.
+template <int P>
+__device__ __forceinline__ float order_parameter(const float (&th)[P])
+{
+    float cs[P], sn[P], C, S;
+    phase_sums<P>(th, cs, sn, C, S);
+    return __builtin_sqrtf(C * C + S * S) * (1.0f / (float)(16 * P));
+}
+
+}  // namespace kuramoto
+}  // namespace sode

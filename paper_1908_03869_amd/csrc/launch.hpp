@@ -27,6 +27,7 @@ struct Request {
     const uint64_t* orbit_seeds;  // device, may be null
     int method;
     int observable;
+    int compensated;  // binary32 coupled kernels: two-sum compensated state
     void* out;  // [orbits][nsave][q]
     hipStream_t stream;
 };
@@ -42,5 +43,28 @@ hipError_t launch_plain_f32(const Request& r);
 // Kuramoto, binary32, Euler-Maruyama: 16 lanes per orbit.
 bool coupled_supports(int n);
 hipError_t launch_kuramoto_coupled_f32(const Request& r);
+
+// Checkpointed forward pass and adjoint of the window-averaged order
+// parameter (Kuramoto, binary32, same sizes as the coupled kernel).
+struct AdjointRequest {
+    int n;
+    const void* X0;        // forward: [orbits][n]
+    const void* p;         // [orbits][d] or [d]
+    int p_per_orbit;
+    int compensated;
+    int64_t orbits;
+    double dt;
+    int64_t nsteps, every, win_lo, win_hi;
+    uint64_t seed, orbit_offset, step_offset;
+    void* ckpt;            // [orbits][nsteps/every + 1][n]
+    double* R;             // forward: [orbits]
+    const double* dL_dR;   // adjoint: [orbits] or null (ones)
+    double* grad;          // adjoint: [d] or null
+    double* grad_rows;     // adjoint: [orbits][d] per-orbit rows (caller's or scratch)
+    float* seg_scratch;    // adjoint: [orbits][every][n]
+    hipStream_t stream;
+};
+hipError_t launch_kuramoto_forward_ckpt_f32(const AdjointRequest& r);
+hipError_t launch_kuramoto_adjoint_f32(const AdjointRequest& r);
 
 }  // namespace sode

@@ -22,9 +22,14 @@ struct sode_ctx {
     int observable = sode::kState;
     int kernel = 0;  // 0 auto, 1 plain, 2 coupled
     int shared_params = 0;
+    int compensated = 1;
     hipError_t last_error = hipSuccess;
     hipStream_t last_stream = nullptr;
     bool launched = false;
+    // Library-owned device scratch (adjoint segment states and per-orbit
+    // gradient rows), grown on demand and released by sode_destroy.
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
 };
 
 namespace {
@@ -60,6 +65,51 @@ bool dims_match(int model, int32_t n, int32_t m, int32_t d)
 }
 
 int status_of(hipError_t e) { return e == hipSuccess ? SODE_OK : SODE_EDEVICE; }
+
+// Make sure the handle owns at least `bytes` of device scratch.  Memory the
+// previous launch on the handle may still use is released only after that
+// launch has finished.
+int ensure_scratch(sode_ctx* h, size_t bytes)
+{
+    if (bytes <= h->scratch_bytes)
+        return SODE_OK;
+    if (h->scratch) {
+        if (h->launched && hipStreamSynchronize(h->last_stream) != hipSuccess)
+            return SODE_EDEVICE;
+        (void)hipFree(h->scratch);
+        h->scratch = nullptr;
+        h->scratch_bytes = 0;
+    }
+    if (hipMalloc(&h->scratch, bytes) != hipSuccess) {
+        h->scratch = nullptr;
+        return SODE_ENOMEM;
+    }
+    h->scratch_bytes = bytes;
+    return SODE_OK;
+}
+
+// Shared argument checks of the checkpointed forward pass and the adjoint.
+int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nsteps,
+                       int64_t every, int64_t win_lo, int64_t win_hi, uint64_t step_offset)
+{
+    if (!h)
+        return SODE_EINVAL;
+    if (orbits < 0 || orbits > kMaxOrbits || nsteps < 1 || every < 1 || nsteps % every != 0)
+        return SODE_EINVAL;
+    if (win_lo < 0 || win_hi < win_lo || win_hi > nsteps)
+        return SODE_EINVAL;
+    if (!std::isfinite(dt) || !(dt > 0.0))
+        return SODE_EINVAL;
+    if (step_offset > (1ull << 32) || (uint64_t)nsteps > (1ull << 32) - step_offset)
+        return SODE_EINVAL;
+    if (h->model != sode::kKuramoto || h->precision != 32 || h->method != sode::kEM ||
+        !sode::coupled_supports(h->n))
+        return SODE_EUNSUPPORTED;
+    // Checkpoints [orbits][nsteps/every + 1][n] must fit 64-bit byte offsets.
+    if (orbits > 0 && nsteps / every + 1 > (INT64_MAX / 16) / orbits / h->n)
+        return SODE_EINVAL;
+    return SODE_OK;
+}
 
 // Which kernel a request goes to; SODE_EUNSUPPORTED if none can run it.
 int choose_kernel(const sode_ctx* h, int* kernel)
@@ -152,6 +202,10 @@ int sode_set_option(sode_t h, const char* key, int64_t value)
         if (value != 0 && value != 1)
             return SODE_EINVAL;
         h->shared_params = (int)value;
+    } else if (std::strcmp(key, "compensated") == 0) {
+        if (value != 0 && value != 1)
+            return SODE_EINVAL;
+        h->compensated = (int)value;
     } else {
         return SODE_EINVAL;
     }
@@ -172,6 +226,8 @@ int sode_get_option(sode_t h, const char* key, int64_t* value)
         *value = h->kernel;
     else if (std::strcmp(key, "shared_params") == 0)
         *value = h->shared_params;
+    else if (std::strcmp(key, "compensated") == 0)
+        *value = h->compensated;
     else
         return SODE_EINVAL;
     return SODE_OK;
@@ -227,6 +283,7 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
     r.orbit_seeds = orbit_seeds;
     r.method = h->method;
     r.observable = h->observable;
+    r.compensated = h->compensated;
     r.out = out;
     r.stream = static_cast<hipStream_t>(stream);
 
@@ -263,8 +320,104 @@ int sode_sync(sode_t h)
     return status_of(h->last_error);
 }
 
+int sode_forward_ckpt(sode_t h, const void* X0, const void* p, int64_t orbits, double t0,
+                      double dt, int64_t nsteps, int64_t ckpt_every, int64_t win_lo,
+                      int64_t win_hi, uint64_t seed, uint64_t orbit_offset, uint64_t step_offset,
+                      void* ckpt, double* R, void* stream)
+{
+    const int st = check_adjoint_args(h, orbits, dt, nsteps, ckpt_every, win_lo, win_hi, step_offset);
+    if (st != SODE_OK)
+        return st;
+    if (!std::isfinite(t0))
+        return SODE_EINVAL;
+    if (orbits == 0)
+        return SODE_OK;
+    if (!X0 || !p || !ckpt || !R)
+        return SODE_EINVAL;
+    sode::AdjointRequest r{};
+    r.n = h->n;
+    r.X0 = X0;
+    r.p = p;
+    r.p_per_orbit = h->shared_params ? 0 : 1;
+    r.compensated = h->compensated;
+    r.orbits = orbits;
+    r.dt = dt;
+    r.nsteps = nsteps;
+    r.every = ckpt_every;
+    r.win_lo = win_lo;
+    r.win_hi = win_hi;
+    r.seed = seed;
+    r.orbit_offset = orbit_offset;
+    r.step_offset = step_offset;
+    r.ckpt = ckpt;
+    r.R = R;
+    r.stream = static_cast<hipStream_t>(stream);
+    const hipError_t e = sode::launch_kuramoto_forward_ckpt_f32(r);
+    h->last_error = e;
+    h->last_stream = r.stream;
+    h->launched = true;
+    return status_of(e);
+}
+
+int sode_adjoint(sode_t h, const void* p, int64_t orbits, double t0, double dt, int64_t nsteps,
+                 int64_t ckpt_every, int64_t win_lo, int64_t win_hi, uint64_t seed,
+                 uint64_t orbit_offset, uint64_t step_offset, const void* ckpt,
+                 const double* dL_dR, double* grad_p, double* grad_p_per_orbit, void* stream)
+{
+    const int st = check_adjoint_args(h, orbits, dt, nsteps, ckpt_every, win_lo, win_hi, step_offset);
+    if (st != SODE_OK)
+        return st;
+    if (!std::isfinite(t0))
+        return SODE_EINVAL;
+    if (!grad_p && !grad_p_per_orbit)
+        return SODE_EINVAL;
+    if (orbits > 0 && (!p || !ckpt))
+        return SODE_EINVAL;
+    const size_t d = 2 * (size_t)h->n + 1;
+    const size_t seg_bytes = (size_t)orbits * (size_t)ckpt_every * (size_t)h->n * sizeof(float);
+    const size_t rows_bytes = grad_p_per_orbit ? 0 : (size_t)orbits * d * sizeof(double);
+    const size_t rows_offset = (seg_bytes + 255) / 256 * 256;
+    const int sc = ensure_scratch(h, rows_offset + rows_bytes + 256);
+    if (sc != SODE_OK)
+        return sc;
+    sode::AdjointRequest r{};
+    r.n = h->n;
+    r.p = p;
+    r.p_per_orbit = h->shared_params ? 0 : 1;
+    r.compensated = h->compensated;
+    r.orbits = orbits;
+    r.dt = dt;
+    r.nsteps = nsteps;
+    r.every = ckpt_every;
+    r.win_lo = win_lo;
+    r.win_hi = win_hi;
+    r.seed = seed;
+    r.orbit_offset = orbit_offset;
+    r.step_offset = step_offset;
+    r.ckpt = const_cast<void*>(ckpt);
+    r.dL_dR = dL_dR;
+    r.grad = grad_p;
+    r.grad_rows = grad_p_per_orbit
+                      ? grad_p_per_orbit
+                      : reinterpret_cast<double*>(static_cast<char*>(h->scratch) + rows_offset);
+    r.seg_scratch = static_cast<float*>(h->scratch);
+    r.stream = static_cast<hipStream_t>(stream);
+    const hipError_t e = sode::launch_kuramoto_adjoint_f32(r);
+    h->last_error = e;
+    h->last_stream = r.stream;
+    h->launched = true;
+    return status_of(e);
+}
+
 int sode_destroy(sode_t h)
 {
+    if (!h)
+        return SODE_OK;
+    if (h->scratch) {
+        if (h->launched)
+            (void)hipStreamSynchronize(h->last_stream);
+        (void)hipFree(h->scratch);
+    }
     delete h;
     return SODE_OK;
 }

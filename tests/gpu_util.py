@@ -28,7 +28,7 @@ def run_library(w: dict, *, precision: int, kernel: str = "auto", method: str = 
                 observable: str | None = None, X0=None, p=None, nsteps=None, stride=None,
                 orbit_offset: int = 0, step_offset: int = 0, t0: float | None = None,
                 orbit_ids=None, orbit_seeds=None, shared: bool | None = None,
-                device="cuda:0") -> np.ndarray:
+                compensated: int = 1, device="cuda:0") -> np.ndarray:
     import torch
 
     dtype = torch.float32 if precision == 32 else torch.float64
@@ -38,7 +38,7 @@ def run_library(w: dict, *, precision: int, kernel: str = "auto", method: str = 
     obs = observable or w.get("observable", "state")
     it = sode.Integrator(w["model"], w["n"], w["m"], w["d"], precision=precision,
                          method=OPT[method], observable=OPT[obs], kernel=OPT[kernel],
-                         shared_params=int(shared))
+                         shared_params=int(shared), compensated=compensated)
     X0_t = torch.tensor(np.ascontiguousarray(X0), dtype=dtype, device=device)
     p_t = torch.tensor(np.ascontiguousarray(p), dtype=dtype, device=device)
     ids = orbit_ids if orbit_ids is not None else w.get("orbit_ids")
@@ -58,13 +58,22 @@ def run_library(w: dict, *, precision: int, kernel: str = "auto", method: str = 
     return res
 
 
+def as_received(a, precision: int):
+    """The values a kernel of the given precision actually receives: binary32
+    kernels get the inputs rounded to float32."""
+    a = np.asarray(a, dtype=np.float64)
+    return a.astype(np.float32).astype(np.float64) if precision == 32 else a
+
+
 def run_oracle(w: dict, *, rows=None, method: str = "em", observable: str | None = None,
                nsteps=None, stride=None, X0=None, p=None, step_offset: int = 0,
-               t0: float | None = None) -> np.ndarray:
+               t0: float | None = None, precision: int = 64) -> np.ndarray:
+    """FP64 oracle on the inputs the library received (rounded to float32
+    for precision 32, so that the comparison measures the integrator)."""
     import oracle
 
-    X0 = np.asarray(w["X0"] if X0 is None else X0)
-    p = np.asarray(w["p"] if p is None else p)
+    X0 = as_received(w["X0"] if X0 is None else X0, precision)
+    p = as_received(w["p"] if p is None else p, precision)
     ids = w.get("orbit_ids")
     sds = w.get("orbit_seeds")
     rows = np.arange(X0.shape[0]) if rows is None else np.asarray(rows)

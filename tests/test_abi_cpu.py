@@ -144,3 +144,52 @@ def test_python_layer_raises_on_error():
 
 def test_destroy_accepts_null():
     assert abi.sode_destroy(None) == 0
+
+
+def _ckpt(h, **kw):
+    a = dict(X0=FAKE, p=FAKE, orbits=16, t0=0.0, dt=1e-3, nsteps=1000, every=100, lo=500,
+             hi=1000, seed=1, ckpt=FAKE, R=FAKE)
+    a.update(kw)
+    return abi.sode_forward_ckpt(h, a["X0"], a["p"], a["orbits"], a["t0"], a["dt"], a["nsteps"],
+                                 a["every"], a["lo"], a["hi"], a["seed"], 0, 0, a["ckpt"], a["R"],
+                                 None)
+
+
+def _adj(h, **kw):
+    a = dict(p=FAKE, orbits=16, t0=0.0, dt=1e-3, nsteps=1000, every=100, lo=500, hi=1000,
+             seed=1, ckpt=FAKE, dLdR=None, grad=FAKE, rows=None)
+    a.update(kw)
+    return abi.sode_adjoint(h, a["p"], a["orbits"], a["t0"], a["dt"], a["nsteps"], a["every"],
+                            a["lo"], a["hi"], a["seed"], 0, 0, a["ckpt"], a["dLdR"], a["grad"],
+                            a["rows"], None)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nsteps=0), dict(every=0), dict(nsteps=1050), dict(lo=-1), dict(hi=1001),
+    dict(lo=600, hi=500), dict(dt=0.0), dict(orbits=-2), dict(t0=float("nan")),
+])
+def test_adjoint_entry_points_reject_bad_arguments(bad):
+    st, h = abi.sode_create("kuramoto", 32, 32, 65)
+    try:
+        assert _ckpt(h, **bad) == abi.SODE_EINVAL
+        assert _adj(h, **bad) == abi.SODE_EINVAL
+    finally:
+        abi.sode_destroy(h)
+
+
+def test_adjoint_entry_points_pointers_and_support():
+    st, h = abi.sode_create("kuramoto", 32, 32, 65)
+    assert _ckpt(h, X0=None) == abi.SODE_EINVAL
+    assert _ckpt(h, R=None) == abi.SODE_EINVAL
+    assert _adj(h, grad=None, rows=None) == abi.SODE_EINVAL
+    assert _ckpt(h, orbits=0, X0=None, p=None, ckpt=None, R=None) == abi.SODE_OK
+    abi.sode_set_option(h, "precision", 64)
+    assert _ckpt(h) == abi.SODE_EUNSUPPORTED
+    assert _adj(h) == abi.SODE_EUNSUPPORTED
+    abi.sode_destroy(h)
+    st, h = abi.sode_create("kuramoto", 12, 12, 25)
+    assert _ckpt(h) == abi.SODE_EUNSUPPORTED
+    abi.sode_destroy(h)
+    st, h = abi.sode_create("ou", 4, 4, 3)
+    assert _adj(h) == abi.SODE_EUNSUPPORTED
+    abi.sode_destroy(h)

@@ -1,0 +1,183 @@
+"""Pathwise adjoint on the GPU against the FP64 oracle adjoint and against
+central finite differences of the FP64 forward map (common random numbers).
+
+Workload: n = m = 32 Kuramoto, orbits sharing (omega, K, sigma), dt = 1e-3,
+10^4 steps, checkpoints every 100 steps, R_o = mean of r over t in [5, 10]
+(steps 5000..10000), loss = mean_o (R_o - 0.6)^2.  Tolerance: relative error
+<= 1e-3 of the gradient (the workload's stated bound).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import as_received, log, run_library, threads
+
+pytestmark = pytest.mark.gpu
+
+
+def _tensors(w, rows=None):
+    import torch
+    X0 = w["X0"] if rows is None else w["X0"][rows]
+    p = w["p"]
+    return (torch.tensor(np.ascontiguousarray(X0), dtype=torch.float32, device="cuda"),
+            torch.tensor(p, dtype=torch.float32, device="cuda"))
+
+
+def _integrator(n):
+    import paper_1908_03869_amd as sode
+    return sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, shared_params=1)
+
+
+def test_checkpoints_equal_integrated_states(gpu):
+    """The checkpointed forward pass steps exactly like sode_integrate, and
+    its binary64 window average matches the oracle's."""
+    import oracle
+    w = workloads.kuramoto_adjoint(orbits=40)
+    X0, p = _tensors(w)
+    it = _integrator(32)
+    log("forward_ckpt vs integrate, 40 orbits x 600 steps")
+    ckpt, R = it.forward_ckpt(X0, p, 0.0, w["dt"], 600, 100, 300, 600, w["seed"])
+    it.sync()
+    states = run_library(dict(w, observable="state"), precision=32, kernel="coupled",
+                         nsteps=600, stride=100, shared=True)
+    np.testing.assert_array_equal(ckpt.double().cpu().numpy(), states)
+    Rref, _, _ = oracle.kuramoto_adjoint(32, as_received(w["X0"], 32), as_received(w["p"], 32),
+                                         0.0, w["dt"], 600, 300, 600, w["seed"], per_orbit=False)
+    assert np.max(np.abs(R.cpu().numpy() - Rref)) <= 1e-5
+
+
+def test_adjoint_matches_fp64_oracle_adjoint(gpu):
+    """64 orbits of the full workload: GPU (FP32 state, FP64 accumulation)
+    against the FP64 oracle adjoint, per orbit and summed."""
+    import oracle
+    w = workloads.kuramoto_adjoint()
+    rows = np.arange(64)
+    X0, p = _tensors(w, rows)
+    it = _integrator(32)
+    args = (0.0, w["dt"], w["nsteps"], w["ckpt_every"], w["win_lo"], w["win_hi"], w["seed"])
+    log("adjoint vs oracle, 64 orbits x 1e4 steps")
+    ckpt, R = it.forward_ckpt(X0, p, *args)
+    dLdR = 2.0 * (R - w["target"]) / len(rows)
+    grad, per = it.adjoint(p, ckpt, *args, dL_dR=dLdR, per_orbit=True)
+    it.sync()
+    Rg = R.cpu().numpy()
+    Rref, gref, pref = oracle.kuramoto_adjoint_parallel(
+        32, as_received(w["X0"][rows], 32), as_received(w["p"], 32), 0.0, w["dt"], w["nsteps"],
+        w["win_lo"], w["win_hi"],
+        w["seed"], dL_dR=2.0 * (Rg - w["target"]) / len(rows), threads=threads())
+    # R is a mean of order parameters: held to the 1e-4 bound of r itself.
+    assert np.max(np.abs(Rg - Rref)) <= 1e-4
+    g = grad.cpu().numpy()
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    print(f"relative L2 error of the summed gradient: {rel:.3e}")
+    assert rel <= 1e-3, rel
+    np.testing.assert_allclose(per.cpu().numpy().sum(axis=0), g, rtol=1e-12, atol=1e-15)
+
+
+def _fd_loss(w, p64, h_dirs, device="cuda"):
+    """Loss of the FP64 plain kernel for p64 + s h v, s = +-1, for each (h, v)."""
+    import torch
+    import paper_1908_03869_amd as sode
+    n = w["n"]
+    it = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=64, observable="kuramoto_r",
+                         kernel="plain", shared_params=1)
+    X0 = torch.tensor(as_received(w["X0"], 32), dtype=torch.float64, device=device)
+    out = torch.empty((X0.shape[0], w["nsteps"] + 1, 1), dtype=torch.float64, device=device)
+    res = []
+    for h, v in h_dirs:
+        vals = []
+        for s in (1.0, -1.0):
+            pt = torch.tensor(p64 + s * h * v, dtype=torch.float64, device=device)
+            it.integrate(X0, pt, 0.0, w["dt"], w["nsteps"], 1, w["seed"], out=out)
+            R = out[:, w["win_lo"]:w["win_hi"] + 1, 0].mean(dim=1)
+            vals.append(float(((R - w["target"]) ** 2).mean()))
+        res.append((vals[0] - vals[1]) / (2 * h))
+    it.close()
+    return np.array(res)
+
+
+def _full_gradient():
+    """Loss gradient of the full workload through the autograd Function."""
+    import torch
+    import paper_1908_03869_amd as sode
+    w = workloads.kuramoto_adjoint()
+    X0, p = _tensors(w)
+    p.requires_grad_(True)
+    it = _integrator(32)
+    R = sode.KuramotoWindowR.apply(p, X0, it, 0.0, w["dt"], w["nsteps"], w["ckpt_every"],
+                                   w["win_lo"], w["win_hi"], w["seed"])
+    loss = ((R - w["target"]) ** 2).mean()
+    loss.backward()
+    return w, float(loss), p.grad.double().cpu().numpy()
+
+
+def test_adjoint_full_workload_vs_stored_oracle_gradient(gpu):
+    """All 4096 orbits: the GPU loss gradient against the FP64 oracle adjoint
+    over the same orbits (stored by tests/golden/make_adjoint_golden.py)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "kuramoto_adjoint_n32.json")) as f:
+        ref = json.load(f)
+    log("adjoint full workload vs stored oracle gradient")
+    w, loss, g = _full_gradient()
+    gref = np.array(ref["grad"])
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    print(f"loss {loss:.8f} (oracle {ref['loss']:.8f}); gradient rel L2 error {rel:.3e}")
+    assert abs(loss - ref["loss"]) <= 1e-4 * ref["loss"]
+    assert rel <= 1e-3, rel
+
+
+def test_adjoint_full_workload_vs_central_differences(gpu):
+    """All 4096 orbits: directional derivatives against central differences
+    of the FP64 plain kernel on the same (float32-rounded) inputs.  With
+    h = 1e-4 the differences are truncation-limited in directions where a
+    few orbits sit near a phase slip (their per-orbit sensitivities are
+    large), so the bound is checked at h = 1e-6, where FP64 rounding still
+    contributes < 1e-10; the h = 1e-4 values are printed alongside.  The
+    bound is the workload's relative error, taken over the vector of
+    directional derivatives."""
+    w, loss, g = _full_gradient()
+    n, d = 32, 65
+    rng = np.random.default_rng(3)
+    dirs = []
+    for q in (0, 1, 17):
+        v = np.zeros(d)
+        v[q] = 1.0
+        dirs.append(v)
+    v = np.zeros(d)
+    v[n + 1:] = 1.0  # the shared noise strength
+    dirs.append(v)
+    v = rng.standard_normal(d)
+    dirs.append(v / np.linalg.norm(v))
+    log("finite differences, FP64 plain kernel, 20 runs")
+    base = as_received(w["p"], 32)
+    fd6 = _fd_loss(w, base, [(1e-6, v) for v in dirs])
+    fd4 = _fd_loss(w, base, [(1e-4, v) for v in dirs])
+    ad = np.array([g @ v for v in dirs])
+    print("adjoint      ", ad)
+    print("FD h = 1e-6  ", fd6)
+    print("FD h = 1e-4  ", fd4)
+    rel = np.linalg.norm(ad - fd6) / np.linalg.norm(fd6)
+    print(f"relative error over the directions: {rel:.3e}")
+    assert rel <= 1e-3, (ad, fd6)
+
+
+def test_per_orbit_parameters_give_per_orbit_rows(gpu):
+    """p as [orbits, d]: the Function returns each orbit's own gradient row,
+    equal to the per-orbit rows of the shared-parameter adjoint."""
+    import torch
+    import paper_1908_03869_amd as sode
+    w = workloads.kuramoto_adjoint(orbits=48)
+    w = dict(w, nsteps=1000, win_lo=500, win_hi=1000)
+    X0, p = _tensors(w)
+    it = _integrator(32)
+    args = (0.0, w["dt"], w["nsteps"], w["ckpt_every"], w["win_lo"], w["win_hi"], w["seed"])
+    ckpt, R = it.forward_ckpt(X0, p, *args)
+    _, rows = it.adjoint(p, ckpt, *args, per_orbit=True)
+    P = p.detach().repeat(48, 1).contiguous().requires_grad_(True)
+    R2 = sode.KuramotoWindowR.apply(P, X0, it, *args)
+    R2.sum().backward()
+    it.sync()
+    np.testing.assert_array_equal(R2.detach().cpu().numpy(), R.cpu().numpy())
+    np.testing.assert_allclose(P.grad.double().cpu().numpy(), rows.float().double().cpu().numpy(),
+                               rtol=1e-6, atol=1e-12)

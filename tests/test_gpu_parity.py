@@ -62,7 +62,7 @@ def test_plain_fp32_ou(gpu):
              p=np.array([1.0, 0.5, 0.3]), t0=0.0, dt=1e-2, nsteps=300, stride=30, seed=7)
     log("plain fp32 ou")
     got = run_library(w, precision=32)
-    want = run_oracle(w)
+    want = run_oracle(w, precision=32)
     assert np.max(np.abs(got - want)) <= 1e-5
 
 
@@ -117,7 +117,7 @@ def test_coupled_fp32_state(gpu, n):
     w = _grid(7, 11, n, 2000)
     log(f"coupled fp32 state n={n}")
     got = run_library(w, precision=32, kernel="coupled", observable="state")
-    want = run_oracle(w, observable="state")
+    want = run_oracle(w, observable="state", precision=32)
     err = circular_diff(got, want)
     assert err.max() <= 1e-3, err.max()
     # Saved phases are wrapped to [-pi, pi].
@@ -128,7 +128,7 @@ def test_coupled_fp32_order_parameter(gpu):
     w = _grid(9, 9, 64, 4000)
     log("coupled fp32 r n=64, 81 orbits x 4000 steps")
     got = run_library(w, precision=32, kernel="coupled")
-    want = run_oracle(w)
+    want = run_oracle(w, precision=32)
     err = np.abs(got - want)
     assert err.max() <= 1e-4, err.max()
 
@@ -146,42 +146,63 @@ def test_kuramoto_grid_full_size_sampled(gpu):
     assert got.shape == (65536, 201, 1)
     assert np.all(np.isfinite(got)) and got.min() >= 0.0 and got.max() <= 1.0 + 1e-6
     rows = w["diagonal"][::11]
-    want = run_oracle(w, rows=rows)
+    want = run_oracle(w, rows=rows, precision=32)
     err = np.abs(got[rows] - want)
     assert err[:, -1].max() <= 1e-4, err[:, -1].max()
     assert err.max() <= 1e-3, err.max()
 
 
 # --------------------------------------------------------------------------- addressing
-@pytest.mark.parametrize("precision,kernel", [(64, "plain"), (32, "coupled"), (32, "plain")])
-def test_replay_resume_shards_independence(gpu, precision, kernel):
+@pytest.mark.parametrize("precision,kernel,comp", [(64, "plain", 0), (32, "coupled", 0),
+                                                   (32, "coupled", 1), (32, "plain", 0)])
+def test_replay_resume_shards_independence(gpu, precision, kernel, comp):
     """Counter-based noise makes results bitwise reproducible: the same call
-    twice; 2N steps == N steps then N more with step_offset; one call == two
-    calls over disjoint orbit ranges with orbit_offset; an orbit's output does
-    not depend on the other orbits' inputs."""
+    twice; one call == two calls over disjoint orbit ranges with orbit_offset;
+    an orbit's output does not depend on the other orbits' inputs; 2N steps
+    == N steps then N more with step_offset (bitwise with a single binary32
+    phase; with compensation the resumed run restarts the trailing part, so
+    it agrees to within a few binary32 ulps)."""
     w = _grid(5, 7, 32, 400)
     w = dict(w, observable="state")
-    log(f"addressing {precision} {kernel}")
-    full = run_library(w, precision=precision, kernel=kernel)
-    again = run_library(w, precision=precision, kernel=kernel)
+    kw = dict(precision=precision, kernel=kernel, compensated=comp)
+    log(f"addressing {precision} {kernel} compensated={comp}")
+    full = run_library(w, **kw)
+    again = run_library(w, **kw)
     np.testing.assert_array_equal(full, again)
 
-    half = run_library(w, precision=precision, kernel=kernel, nsteps=200)
-    rest = run_library(w, precision=precision, kernel=kernel, X0=half[:, -1], nsteps=200,
-                       step_offset=200, t0=0.2)
-    np.testing.assert_array_equal(rest[:, -1], full[:, -1])
+    half = run_library(w, nsteps=200, **kw)
+    rest = run_library(w, X0=half[:, -1], nsteps=200, step_offset=200, t0=0.2, **kw)
+    if comp:
+        assert circular_diff(rest[:, -1], full[:, -1]).max() <= 2e-6
+    else:
+        np.testing.assert_array_equal(rest[:, -1], full[:, -1])
 
-    a = run_library(w, precision=precision, kernel=kernel, X0=w["X0"][:13], p=w["p"][:13])
-    b = run_library(w, precision=precision, kernel=kernel, X0=w["X0"][13:], p=w["p"][13:],
-                    orbit_offset=13)
+    a = run_library(w, X0=w["X0"][:13], p=w["p"][:13], **kw)
+    b = run_library(w, X0=w["X0"][13:], p=w["p"][13:], orbit_offset=13, **kw)
     np.testing.assert_array_equal(np.concatenate([a, b]), full)
 
     X0 = w["X0"].copy()
     p = w["p"].copy()
     X0[1:] += 0.5
     p[1:, 0] *= 0.5
-    one = run_library(w, precision=precision, kernel=kernel, X0=X0, p=p)
+    one = run_library(w, X0=X0, p=p, **kw)
     np.testing.assert_array_equal(one[0], full[0])
+
+
+def test_compensation_tightens_the_fp32_trajectory(gpu):
+    """Uncoupled orbits (K = 0: no chaotic amplification, errors add up
+    linearly): with the two-sum state the binary32 phases track the FP64
+    oracle far more closely than a single rounded phase, whose rounding
+    random-walks over the 4000 steps."""
+    w = _grid(1, 16, 64, 4000)
+    w = dict(w, observable="state")
+    log("compensated vs single binary32 phases, K = 0")
+    ref = run_oracle(w, precision=32)
+    e_single = circular_diff(run_library(w, precision=32, kernel="coupled", compensated=0), ref)
+    e_comp = circular_diff(run_library(w, precision=32, kernel="coupled", compensated=1), ref)
+    rms_s, rms_c = np.sqrt((e_single ** 2).mean()), np.sqrt((e_comp ** 2).mean())
+    print(f"rms |dtheta| after 4000 steps: single {rms_s:.2e}, compensated {rms_c:.2e}")
+    assert rms_c < 0.2 * rms_s
 
 
 @pytest.mark.parametrize("precision,kernel", [(64, "plain"), (32, "coupled")])
@@ -195,7 +216,7 @@ def test_edge_sizes(gpu, precision, kernel):
     want0 = np.remainder(w["X0"] + math.pi, 2 * math.pi) - math.pi
     assert circular_diff(zero[0, 0], want0[0]).max() <= 1e-6
     one = run_library(w, precision=precision, kernel=kernel, nsteps=300, stride=300)
-    ref = run_oracle(w, nsteps=300, stride=300)
+    ref = run_oracle(w, nsteps=300, stride=300, precision=precision)
     tol = 1e-10 if precision == 64 else 1e-4
     assert circular_diff(one, ref).max() <= tol
 
