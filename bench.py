@@ -99,6 +99,54 @@ def adjoint_leg(sode, torch, workloads, dev, reps: int = 3) -> dict:
             "grad_norm": float(grad.norm())}
 
 
+def ragged_leg(sode, torch, workloads, dev, reps: int = 5) -> dict:
+    """Makespan of the 4096-instance FitzHugh-Nagumo batch in one persistent,
+    graph-captured launch (autotuned on the first, untimed call), and the
+    longest instance run alone: the batch cannot finish before it."""
+    w = workloads.fhn_ragged()
+    idx = np.arange(len(w["units"]))
+    b = sode.RaggedBatch(2 * w["units"], w["nsteps"], w["stride"], w["seed"],
+                         idx.astype(np.uint32), d=5)
+    X0 = torch.tensor(b.pack(w["X0"]), dtype=torch.float32, device=dev)
+    p = torch.tensor(b.pack(w["params"]), dtype=torch.float32, device=dev)
+    it = sode.Integrator("fhn", 256, 128, 5, precision=32)
+    out = it.integrate_ragged(b, X0, p, 0.0, w["dt"])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        it.integrate_ragged(b, X0, p, 0.0, w["dt"], out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    cfg = (it.get_option("ragged_waves_per_cu"), it.get_option("ragged_units_per_lane"))
+    unit_steps = int((w["units"] * w["nsteps"]).sum())
+    # Critical path: the instance with the most units x steps, alone.
+    j = int(np.argmax(w["units"] * w["nsteps"]))
+    b1 = sode.RaggedBatch([2 * w["units"][j]], [w["nsteps"][j]], w["stride"], w["seed"], [j], d=5)
+    X1 = torch.tensor(b1.pack([w["X0"][j]]), dtype=torch.float32, device=dev)
+    p1 = torch.tensor(b1.pack([w["params"][j]]), dtype=torch.float32, device=dev)
+    it1 = sode.Integrator("fhn", 256, 128, 5, precision=32, waves_per_cu=cfg[0],
+                          units_per_lane=cfg[1])
+    it1.integrate_ragged(b1, X1, p1, 0.0, w["dt"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    it1.integrate_ragged(b1, X1, p1, 0.0, w["dt"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    alone = e0.elapsed_time(e1)
+    return {"workload": "fhn_ragged_4096", "instances": b.count, "unit_steps": unit_steps,
+            "makespan_ms": ms, "unit_steps_per_s": unit_steps / (ms * 1e-3),
+            "waves_per_cu": cfg[0], "units_per_lane": cfg[1],
+            "longest_instance_alone_ms": alone,
+            "longest_instance": {"units": int(w["units"][j]), "nsteps": int(w["nsteps"][j])},
+            "makespan_over_longest": ms / alone}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +232,7 @@ def main():
     plain_rate = orbits * bsteps / (plain_ms * 1e-3)
 
     adj = adjoint_leg(sode, torch, workloads, dev)
+    rag = ragged_leg(sode, torch, workloads, dev)
 
     cpu = None
     err = None
@@ -231,6 +280,7 @@ def main():
                        "speedup_of_value": value / plain_rate},
         "error": {"max_abs_dr_final": err, "tolerance": 1e-4},
         "adjoint": adj,
+        "ragged": rag,
     }
     print(json.dumps(line))
 

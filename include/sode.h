@@ -33,6 +33,23 @@ extern "C" {
 
 typedef struct sode_ctx* sode_t; /* opaque, owned by the library */
 
+/*
+ * One instance of a ragged batch (sode_integrate_ragged): its own size,
+ * length, save stride, noise stream and places in packed arrays.  64 bytes.
+ */
+typedef struct sode_instance {
+    int32_t n;           /* state dimension of this instance (FHN: 2 x units) */
+    int32_t reserved0;   /* must be 0 */
+    int64_t nsteps;      /* >= 0, a multiple of stride, < 2^32 */
+    int64_t stride;      /* >= 1: out holds X^0, X^stride, ..., X^nsteps */
+    int64_t x0_offset;   /* element offset of X0_i [n] in the packed X0 */
+    int64_t p_offset;    /* element offset of p_i [d] in the packed p */
+    int64_t out_offset;  /* element offset of out_i [nsteps/stride + 1][n] in out */
+    uint64_t seed;       /* Philox key of the instance */
+    uint32_t orbit_id;   /* Philox counter word 1 of the instance */
+    uint32_t reserved1;  /* must be 0 */
+} sode_instance_t;
+
 enum sode_status {
     SODE_OK = 0,
     SODE_EINVAL = -1,       /* invalid argument (shape, pointer, option)        */
@@ -84,12 +101,12 @@ int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out)
  *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
  *                  used by every orbit.
  *   "compensated"  binary32 Kuramoto kernels (coupled, forward_ckpt,
- *                  adjoint): 1 (default) carries each phase as hi + lo and
- *                  adds every increment with an error-free two-sum, so the
- *                  trajectory stays within ~1e-9 rad of exact arithmetic
- *                  (saved states hold hi; resuming from them restarts lo at
- *                  0); 0 keeps a single binary32 phase (saved states resume
- *                  bit-exactly).
+ *                  adjoint) and the ragged FHN kernel: 1 (default) carries
+ *                  each state variable as hi + lo and adds every increment
+ *                  with an error-free two-sum, so rounding no longer
+ *                  accumulates over the steps (saved states hold hi;
+ *                  resuming from them restarts lo at 0); 0 keeps a single
+ *                  binary32 value (saved states resume bit-exactly).
  * Unknown keys or values give SODE_EINVAL and leave the handle unchanged.
  */
 int sode_set_option(sode_t h, const char* key, int64_t value);
@@ -181,6 +198,31 @@ int sode_adjoint(sode_t h, const void* p, int64_t orbits, double t0, double dt, 
                  int64_t ckpt_every, int64_t win_lo, int64_t win_hi, uint64_t seed,
                  uint64_t orbit_offset, uint64_t step_offset, const void* ckpt,
                  const double* dL_dR, double* grad_p, double* grad_p_per_orbit, void* stream);
+
+/*
+ * sode_integrate_ragged - integrate a batch of instances of uneven size and
+ * length in one persistent launch (the paper runs one size per launch and
+ * tunes the work-group size by hand, Sec. 2.2.2 and Table 4).
+ *
+ * Handle: model "fhn", precision 32 (else SODE_EUNSUPPORTED); every
+ * instance has an even n with 2 <= n <= min(256, handle n), m = n/2, d = 5.
+ *   inst   HOST array [count] of descriptors (read during the call only).
+ *   X0, p, out  packed DEVICE arrays of x0_len, p_len, out_len floats; every
+ *          instance's slices must lie inside them (else SODE_EINVAL).
+ * Instance i uses the noise of sode_integrate_ex with orbit id
+ * inst[i].orbit_id and seed inst[i].seed; time t_k = t0 + k dt.
+ *
+ * Instances are grouped by lane shape and scheduled longest first through
+ * a device work queue.  Options: "waves_per_cu" and "units_per_lane"
+ * (0 = chosen by the built-in autotuner on the first call for a batch
+ * shape, then cached in the handle); "graph" (1 = capture the launch in a
+ * HIP graph and replay it for identical calls); "persistent" (0 = one
+ * block per group, no queue: bitwise the same results, for testing).  The
+ * handle keeps device copies of the schedule; rebuilding them may allocate.
+ */
+int sode_integrate_ragged(sode_t h, const sode_instance_t* inst, int32_t count, const void* X0,
+                          int64_t x0_len, const void* p, int64_t p_len, void* out,
+                          int64_t out_len, double t0, double dt, void* stream);
 
 /*
  * sode_sync - wait for the handle's last launch and report device errors.

@@ -10,7 +10,8 @@ from __future__ import annotations
 from . import abi
 from .abi import SodeError, check
 
-__all__ = ["abi", "Integrator", "SodeError", "check", "OPTION_VALUES", "KuramotoWindowR"]
+__all__ = ["abi", "Integrator", "SodeError", "check", "OPTION_VALUES", "KuramotoWindowR",
+           "RaggedBatch"]
 
 OPTION_VALUES = {
     "method": {"em": 0, "rk4": 1},
@@ -32,7 +33,8 @@ class Integrator:
         self.handle = h
         self.model, self.n, self.m, self.d = model, n, m, d
         self.options = {"precision": 32, "method": 0, "observable": 0, "kernel": 0,
-                        "shared_params": 0, "compensated": 1}
+                        "shared_params": 0, "compensated": 1, "waves_per_cu": 0,
+                        "units_per_lane": 0, "graph": 1, "persistent": 1}
         for k, v in options.items():
             self.set_option(k, v)
 
@@ -124,6 +126,28 @@ class Integrator:
         check(st, "sode_adjoint")
         return grad, rows
 
+    def integrate_ragged(self, batch: "RaggedBatch", X0, p, t0: float, dt: float, *, out=None,
+                         stream=None):
+        """sode_integrate_ragged over a packed batch; returns the packed out."""
+        import torch
+        for name, t in (("X0", X0), ("p", p)):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
+        if out is None:
+            out = torch.empty(batch.out_len, dtype=torch.float32, device=X0.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(X0.device).cuda_stream
+        st = abi.sode_integrate_ragged(self.handle, batch.desc, batch.count, X0.data_ptr(),
+                                       X0.numel(), p.data_ptr(), p.numel(), out.data_ptr(),
+                                       out.numel(), t0, dt, stream)
+        check(st, "sode_integrate_ragged")
+        return out
+
+    def get_option(self, key: str) -> int:
+        st, v = abi.sode_get_option(self.handle, key)
+        check(st, f"sode_get_option({key})")
+        return v
+
     def sync(self) -> None:
         check(abi.sode_sync(self.handle), "sode_sync")
 
@@ -137,6 +161,49 @@ class Integrator:
             self.close()
         except Exception:
             pass
+
+
+class RaggedBatch:
+    """Descriptors (sode_instance_t) of a ragged batch plus its packing.
+
+    ``n[i]`` is the state dimension of instance i; X0 and p of all instances
+    are packed back to back (instance order), and so are the outputs
+    [nsteps/stride+1][n] of each instance."""
+
+    def __init__(self, n, nsteps, stride, seeds, orbit_ids, d: int):
+        import ctypes
+        import numpy as np
+        n = np.asarray(n, dtype=np.int64)
+        nsteps = np.asarray(nsteps, dtype=np.int64)
+        stride = np.broadcast_to(np.asarray(stride, dtype=np.int64), n.shape)
+        self.count = int(n.size)
+        self.n, self.nsteps, self.stride, self.d = n, nsteps, stride, d
+        self.x0_offset = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+        self.p_offset = np.arange(self.count, dtype=np.int64) * d
+        sizes = (nsteps // stride + 1) * n
+        self.out_offset = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        self.x0_len = int(n.sum())
+        self.p_len = self.count * d
+        self.out_len = int(sizes.sum())
+        seeds = np.broadcast_to(np.asarray(seeds, dtype=np.uint64), n.shape)
+        ids = np.broadcast_to(np.asarray(orbit_ids, dtype=np.uint32), n.shape)
+        self.desc = (abi.SodeInstance * max(self.count, 1))()
+        for i in range(self.count):
+            e = self.desc[i]
+            e.n, e.nsteps, e.stride = int(n[i]), int(nsteps[i]), int(stride[i])
+            e.x0_offset, e.p_offset = int(self.x0_offset[i]), int(self.p_offset[i])
+            e.out_offset, e.seed, e.orbit_id = int(self.out_offset[i]), int(seeds[i]), int(ids[i])
+        self._keep = ctypes.addressof(self.desc)
+
+    def pack(self, per_instance):
+        import numpy as np
+        return np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in per_instance])
+
+    def unpack(self, out_flat, i: int):
+        """Output of instance i as [nsteps/stride+1, n]."""
+        a = int(self.out_offset[i])
+        ns = int(self.nsteps[i] // self.stride[i] + 1)
+        return out_flat[a:a + ns * int(self.n[i])].reshape(ns, int(self.n[i]))
 
 
 def _window_r_function():

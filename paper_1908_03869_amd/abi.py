@@ -23,9 +23,21 @@ SODE_ENONFINITE = -5
 # Every symbol include/sode.h declares.
 EXPORTS = (
     "sode_create", "sode_set_option", "sode_get_option", "sode_integrate",
-    "sode_integrate_ex", "sode_forward_ckpt", "sode_adjoint", "sode_sync", "sode_destroy",
-    "sode_strerror", "sode_version",
+    "sode_integrate_ex", "sode_forward_ckpt", "sode_adjoint", "sode_integrate_ragged",
+    "sode_sync", "sode_destroy", "sode_strerror", "sode_version",
 )
+
+
+class SodeInstance(ctypes.Structure):
+    """sode_instance_t: one instance of a ragged batch (64 bytes)."""
+    _fields_ = [("n", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("nsteps", ctypes.c_int64), ("stride", ctypes.c_int64),
+                ("x0_offset", ctypes.c_int64), ("p_offset", ctypes.c_int64),
+                ("out_offset", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("orbit_id", ctypes.c_uint32), ("reserved1", ctypes.c_uint32)]
+
+
+assert ctypes.sizeof(SodeInstance) == 64
 
 _lib = None
 
@@ -65,6 +77,9 @@ def load() -> ctypes.CDLL:
     L.sode_adjoint.argtypes = [vp, vp, i64, f64, f64, i64, i64, i64, i64, u64, u64, u64, vp, vp,
                                vp, vp, vp]
     L.sode_adjoint.restype = ctypes.c_int
+    L.sode_integrate_ragged.argtypes = [vp, ctypes.POINTER(SodeInstance), ctypes.c_int32, vp, i64,
+                                        vp, i64, vp, i64, f64, f64, vp]
+    L.sode_integrate_ragged.restype = ctypes.c_int
     L.sode_sync.argtypes = [vp]
     L.sode_sync.restype = ctypes.c_int
     L.sode_destroy.argtypes = [vp]
@@ -116,6 +131,12 @@ def sode_adjoint(h, p, orbits, t0, dt, nsteps, ckpt_every, win_lo, win_hi, seed,
     return load().sode_adjoint(h, p, orbits, t0, dt, nsteps, ckpt_every, win_lo, win_hi, seed,
                                orbit_offset, step_offset, ckpt, dL_dR, grad_p, grad_p_per_orbit,
                                stream)
+
+
+def sode_integrate_ragged(h, inst, count, X0, x0_len, p, p_len, out, out_len, t0, dt,
+                          stream) -> int:
+    return load().sode_integrate_ragged(h, inst, count, X0, x0_len, p, p_len, out, out_len, t0,
+                                        dt, stream)
 
 
 def sode_sync(h) -> int:

@@ -1,0 +1,54 @@
+// ctx.hpp - the handle behind sode_t (internal to libsode).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+
+#include "launch.hpp"
+
+struct sode_ctx {
+    int model;
+    int32_t n, m, d;
+    int precision = 32;
+    int method = sode::kEM;
+    int observable = sode::kState;
+    int kernel = 0;  // 0 auto, 1 plain, 2 coupled
+    int shared_params = 0;
+    int compensated = 1;
+    // Ragged batches: 0 = autotuned.
+    int waves_per_cu = 0;
+    int units_per_lane = 0;
+    int graph = 1;
+    int persistent = 1;
+
+    hipError_t last_error = hipSuccess;
+    hipStream_t last_stream = nullptr;
+    bool launched = false;
+
+    // Device scratch of the adjoint (segment states, per-orbit rows).
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+
+    // Device copy of the current ragged schedule:
+    // [descriptors | group slots | group shapes | queue counter].
+    void* rg_buf = nullptr;
+    size_t rg_bytes = 0;
+    size_t rg_slots_off = 0, rg_shape_off = 0, rg_counter_off = 0;
+    uint64_t rg_plan_key = 0;
+    int32_t rg_ngroups = 0;
+    // Autotuner results, keyed by the batch shape: (waves per CU, units).
+    std::map<uint64_t, std::pair<int, int>> rg_tuned;
+    int rg_last_waves = 0, rg_last_units = 0;
+    // Captured launch and the call it belongs to.
+    hipGraph_t rg_graph = nullptr;
+    hipGraphExec_t rg_exec = nullptr;
+    uint64_t rg_graph_key = 0;
+    hipStream_t rg_capture = nullptr;
+};
+
+namespace sode {
+void release_ragged(sode_ctx* h);
+}

@@ -1,0 +1,218 @@
+// fhn_ragged.hip - one persistent launch for a ragged batch of stochastic
+// FitzHugh-Nagumo chains of different sizes and lengths (Euler-Maruyama,
+// binary32).  Chain with N units, state (v_1..v_N, w_1..w_N):
+//     dv_i = [v_i - v_i^3/3 - w_i + D (v_{i-1} - 2 v_i + v_{i+1})] dt + sigma dW_i
+//     dw_i = eps (v_i + a - b w_i) dt,   no-flux ends (v_0 = v_1, v_{N+1} = v_N).
+//
+// Mapping.  An instance occupies L consecutive lanes (L = 4, 8 or 16, inside
+// one DPP row) and each lane owns U consecutive units (U = 1, 2, 4 or 8),
+// L * U >= N.  A wave therefore carries 64/L instances of the same (L, U)
+// shape.  The only cross-lane data is the diffusive coupling of the two
+// units at a lane's edges: the left neighbour comes from lane l-1 by
+// row_shr:1, the right one from lane l+1 by row_shl:1.  Reads that cross an
+// instance boundary (or a row boundary) are never used: they only reach
+// units 0 and N-1, whose missing neighbour is replaced by the unit itself
+// (no-flux ends).  Units with index >= N in the last lanes are computed
+// and never stored.
+//
+// Precision.  Near rest the recovery variable moves by ~1e-7 per step,
+// below half a binary32 ulp of w ~ 0.6, so plain binary32 updates stall and
+// drift over 10^5 steps.  With compensation (the handle's default) v and w
+// are carried as hi + lo and every increment is added with an error-free
+// two-sum.
+//
+// Scheduling.  The host groups instances of one shape into groups of 64/L
+// (sorted by step count inside a shape) and orders groups by decreasing
+// cost U x steps (longest processing time first).  Waves of the persistent
+// grid pop groups with one atomic counter until the list is exhausted, so
+// the batch is balanced without knowing in advance which instance finishes
+// when.  The same group body also runs non-persistently (one block per
+// group), which gives bitwise the same result.
+#include "launch.hpp"
+#include "noise.hpp"
+
+#pragma clang fp contract(off)
+
+namespace sode {
+namespace {
+
+constexpr float kThird = 1.0f / 3.0f;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_read(float v)
+{
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+// row_shr:1 -> value of lane l-1; row_shl:1 -> value of lane l+1 (same row).
+__device__ __forceinline__ float from_lower_lane(float v) { return dpp_read<0x111>(v); }
+__device__ __forceinline__ float from_upper_lane(float v) { return dpp_read<0x101>(v); }
+
+// x_hi + x_lo += inc without losing the rounding error of the sum.
+__device__ __forceinline__ void two_sum_add(float& hi, float& lo, float inc)
+{
+    const float y = inc + lo;
+    const float s = hi + y;
+    const float t = s - hi;
+    lo = (hi - (s - t)) + (y - t);
+    hi = s;
+}
+
+template <int L, int U, bool COMP>
+__device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, int lane)
+{
+    const int slot = lane / L;
+    const int l = lane % L;
+    const int32_t inst = a.slots[g * kRaggedSlots + slot];
+    if (inst < 0)
+        return;
+    const sode_instance_t d = a.desc[inst];
+    const int N = d.n / 2;
+    const float* __restrict__ X0 = a.X0 + d.x0_offset;
+    const float* __restrict__ pr = a.p + d.p_offset;
+    float* __restrict__ out = a.out + d.out_offset;
+    const float pa = pr[0], pb = pr[1], eps = pr[2], D = pr[3];
+    const float noise = pr[4] * a.sqdt;
+    const float dt = a.dt;
+
+    float v[U], w[U], vlo[U], wlo[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = U * l + u;
+        v[u] = j < N ? X0[j] : 0.0f;
+        w[u] = j < N ? X0[N + j] : 0.0f;
+        vlo[u] = 0.0f;
+        wlo[u] = 0.0f;
+    }
+    auto save = [&](int64_t s) {
+        float* __restrict__ row = out + s * d.n;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = U * l + u;
+            if (j < N) {
+                row[j] = v[u];
+                row[N + j] = w[u];
+            }
+        }
+    };
+    save(0);
+    const Stream st{d.orbit_id, (uint32_t)d.seed, (uint32_t)(d.seed >> 32)};
+    int64_t s = 1, next_save = d.stride;
+    for (int64_t k = 0; k < d.nsteps; ++k) {
+        float xi[U];
+        lane_normals<U>(st, (uint32_t)k, l, xi);
+        const float left_edge = from_lower_lane(v[U - 1]);
+        const float right_edge = from_upper_lane(v[0]);
+        float dv[U], dw[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = U * l + u;
+            float vl = u > 0 ? v[u - 1] : left_edge;
+            float vr = u < U - 1 ? v[u + 1] : right_edge;
+            vl = j == 0 ? v[u] : vl;
+            vr = j == N - 1 ? v[u] : vr;
+            const float lap = (vl - 2.0f * v[u]) + vr;
+            const float cube = v[u] * v[u] * v[u] * kThird;
+            const float fv = ((v[u] - cube) - w[u]) + D * lap;
+            const float fw = eps * ((v[u] + pa) - pb * w[u]);
+            dv[u] = fv * dt + noise * xi[u];
+            dw[u] = fw * dt;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if constexpr (COMP) {
+                two_sum_add(v[u], vlo[u], dv[u]);
+                two_sum_add(w[u], wlo[u], dw[u]);
+            } else {
+                v[u] = v[u] + dv[u];
+                w[u] = w[u] + dw[u];
+            }
+        }
+        if (k + 1 == next_save) {
+            save(s);
+            ++s;
+            next_save += d.stride;
+        }
+    }
+}
+
+template <bool COMP>
+__device__ __forceinline__ void run_shape(const RaggedKernelArgs& a, int32_t g, int lane)
+{
+    switch (a.shape[g]) {
+    case 0: run_group<4, 1, COMP>(a, g, lane); break;
+    case 1: run_group<4, 2, COMP>(a, g, lane); break;
+    case 2: run_group<4, 4, COMP>(a, g, lane); break;
+    case 3: run_group<4, 8, COMP>(a, g, lane); break;
+    case 4: run_group<8, 1, COMP>(a, g, lane); break;
+    case 5: run_group<8, 2, COMP>(a, g, lane); break;
+    case 6: run_group<8, 4, COMP>(a, g, lane); break;
+    case 7: run_group<8, 8, COMP>(a, g, lane); break;
+    case 8: run_group<16, 1, COMP>(a, g, lane); break;
+    case 9: run_group<16, 2, COMP>(a, g, lane); break;
+    case 10: run_group<16, 4, COMP>(a, g, lane); break;
+    case 11: run_group<16, 8, COMP>(a, g, lane); break;
+    default: break;
+    }
+}
+
+__device__ __forceinline__ void run_any(const RaggedKernelArgs& a, int32_t g, int lane)
+{
+    if (a.compensated)
+        run_shape<true>(a, g, lane);
+    else
+        run_shape<false>(a, g, lane);
+}
+
+// Persistent: every wave pops group indices until the list is exhausted
+// (an exit every wave reaches).  Lane 0 takes the ticket with a vector
+// atomic and the wave reads it back as a uniform value.
+__global__ __launch_bounds__(64) void fhn_ragged_persistent(const RaggedKernelArgs a)
+{
+    const int lane = threadIdx.x;
+    for (;;) {
+        uint32_t ticket = 0;
+        if (lane == 0)
+            ticket = atomicAdd(a.counter, 1u);
+        const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
+        if (g >= (uint32_t)a.ngroups)
+            break;
+        run_any(a, (int32_t)g, lane);
+    }
+}
+
+// One block per group, no queue: the reference schedule for the tests.
+__global__ __launch_bounds__(64) void fhn_ragged_direct(const RaggedKernelArgs a)
+{
+    run_any(a, (int32_t)blockIdx.x, threadIdx.x);
+}
+
+__global__ void reset_counter(uint32_t* c)
+{
+    if (threadIdx.x == 0)
+        *c = 0u;
+}
+
+}  // namespace
+
+int ragged_shape_code(int lanes, int units)
+{
+    const int li = lanes == 4 ? 0 : lanes == 8 ? 1 : 2;
+    const int ui = units == 1 ? 0 : units == 2 ? 1 : units == 4 ? 2 : 3;
+    return li * 4 + ui;
+}
+
+hipError_t launch_fhn_ragged(const RaggedKernelArgs& a, int persistent, int waves, hipStream_t stream)
+{
+    if (a.ngroups <= 0)
+        return hipSuccess;
+    if (persistent) {
+        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, stream, a.counter);
+        hipLaunchKernelGGL(fhn_ragged_persistent, dim3((unsigned)waves), dim3(64), 0, stream, a);
+    } else {
+        hipLaunchKernelGGL(fhn_ragged_direct, dim3((unsigned)a.ngroups), dim3(64), 0, stream, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sode

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sode.h"
+
 namespace sode {
 
 enum ModelId : int { kKuramoto = 0, kOU = 1, kGBM = 2, kFHN = 3, kRNN = 4 };
@@ -66,5 +68,23 @@ struct AdjointRequest {
 };
 hipError_t launch_kuramoto_forward_ckpt_f32(const AdjointRequest& r);
 hipError_t launch_kuramoto_adjoint_f32(const AdjointRequest& r);
+
+// Ragged FitzHugh-Nagumo batches (binary32).  A group is up to
+// kRaggedSlots instances of one lane shape (L lanes x U units per lane).
+constexpr int kRaggedSlots = 16;
+struct RaggedKernelArgs {
+    const sode_instance_t* desc;  // device copy of the descriptors
+    const int32_t* slots;         // [ngroups][kRaggedSlots] instance index or -1
+    const int32_t* shape;         // [ngroups] shape code (ragged_shape_code)
+    uint32_t* counter;            // queue ticket counter
+    int32_t ngroups;
+    const float* X0;
+    const float* p;
+    float* out;
+    float dt, sqdt;
+    int compensated;  // two-sum state (v and w carried as hi + lo)
+};
+int ragged_shape_code(int lanes, int units);
+hipError_t launch_fhn_ragged(const RaggedKernelArgs& a, int persistent, int waves, hipStream_t stream);
 
 }  // namespace sode

@@ -127,4 +127,32 @@ __device__ __forceinline__ void normals(const Stream& st, uint32_t k, int m, R* 
     }
 }
 
+// Normals P*l .. P*l+P-1 of one orbit at global step k, for a lane l that
+// owns P consecutive state components (P = 1, 2 or a multiple of 4): the
+// Philox blocks floor(P*l/4) .. floor((P*l+P-1)/4), of which lanes with
+// P < 4 compute one block and keep their share of it.
+template <int P>
+__device__ __forceinline__ void lane_normals(const Stream& st, uint32_t k, int l, float (&xi)[P])
+{
+    if constexpr (P % 4 == 0) {
+#pragma unroll
+        for (int g = 0; g < P / 4; ++g) {
+            const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)(l * (P / 4) + g), 0u, st.key_lo, st.key_hi);
+            box_muller_f32(w.w0, w.w1, xi[4 * g + 0], xi[4 * g + 1]);
+            box_muller_f32(w.w2, w.w3, xi[4 * g + 2], xi[4 * g + 3]);
+        }
+    } else if constexpr (P == 2) {
+        const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)(l >> 1), 0u, st.key_lo, st.key_hi);
+        const bool upper = (l & 1) != 0;
+        box_muller_f32(upper ? w.w2 : w.w0, upper ? w.w3 : w.w1, xi[0], xi[1]);
+    } else {
+        static_assert(P == 1, "oscillators per lane");
+        const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)(l >> 2), 0u, st.key_lo, st.key_hi);
+        const bool upper = (l & 2) != 0;
+        float zc, zs;
+        box_muller_f32(upper ? w.w2 : w.w0, upper ? w.w3 : w.w1, zc, zs);
+        xi[0] = (l & 1) ? zs : zc;
+    }
+}
+
 }  // namespace sode

@@ -11,26 +11,8 @@
 #include <cstring>
 #include <new>
 
-#include "launch.hpp"
-#include "sode.h"
+#include "ctx.hpp"
 
-struct sode_ctx {
-    int model;
-    int32_t n, m, d;
-    int precision = 32;
-    int method = sode::kEM;
-    int observable = sode::kState;
-    int kernel = 0;  // 0 auto, 1 plain, 2 coupled
-    int shared_params = 0;
-    int compensated = 1;
-    hipError_t last_error = hipSuccess;
-    hipStream_t last_stream = nullptr;
-    bool launched = false;
-    // Library-owned device scratch (adjoint segment states and per-orbit
-    // gradient rows), grown on demand and released by sode_destroy.
-    void* scratch = nullptr;
-    size_t scratch_bytes = 0;
-};
 
 namespace {
 
@@ -206,6 +188,22 @@ int sode_set_option(sode_t h, const char* key, int64_t value)
         if (value != 0 && value != 1)
             return SODE_EINVAL;
         h->compensated = (int)value;
+    } else if (std::strcmp(key, "waves_per_cu") == 0) {
+        if (value < 0 || value > 32)
+            return SODE_EINVAL;
+        h->waves_per_cu = (int)value;
+    } else if (std::strcmp(key, "units_per_lane") == 0) {
+        if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+            return SODE_EINVAL;
+        h->units_per_lane = (int)value;
+    } else if (std::strcmp(key, "graph") == 0) {
+        if (value != 0 && value != 1)
+            return SODE_EINVAL;
+        h->graph = (int)value;
+    } else if (std::strcmp(key, "persistent") == 0) {
+        if (value != 0 && value != 1)
+            return SODE_EINVAL;
+        h->persistent = (int)value;
     } else {
         return SODE_EINVAL;
     }
@@ -228,6 +226,18 @@ int sode_get_option(sode_t h, const char* key, int64_t* value)
         *value = h->shared_params;
     else if (std::strcmp(key, "compensated") == 0)
         *value = h->compensated;
+    else if (std::strcmp(key, "waves_per_cu") == 0)
+        *value = h->waves_per_cu;
+    else if (std::strcmp(key, "units_per_lane") == 0)
+        *value = h->units_per_lane;
+    else if (std::strcmp(key, "graph") == 0)
+        *value = h->graph;
+    else if (std::strcmp(key, "persistent") == 0)
+        *value = h->persistent;
+    else if (std::strcmp(key, "ragged_waves_per_cu") == 0)
+        *value = h->rg_last_waves;
+    else if (std::strcmp(key, "ragged_units_per_lane") == 0)
+        *value = h->rg_last_units;
     else
         return SODE_EINVAL;
     return SODE_OK;
@@ -413,11 +423,11 @@ int sode_destroy(sode_t h)
 {
     if (!h)
         return SODE_OK;
-    if (h->scratch) {
-        if (h->launched)
-            (void)hipStreamSynchronize(h->last_stream);
+    if (h->launched)
+        (void)hipStreamSynchronize(h->last_stream);
+    if (h->scratch)
         (void)hipFree(h->scratch);
-    }
+    sode::release_ragged(h);
     delete h;
     return SODE_OK;
 }

@@ -193,3 +193,50 @@ def test_adjoint_entry_points_pointers_and_support():
     st, h = abi.sode_create("ou", 4, 4, 3)
     assert _adj(h) == abi.SODE_EUNSUPPORTED
     abi.sode_destroy(h)
+
+
+def _ragged(h, descs, x0_len=1000, p_len=1000, out_len=10**7, dt=1e-3):
+    arr = (abi.SodeInstance * len(descs))(*descs) if descs else None
+    return abi.sode_integrate_ragged(h, arr, len(descs), FAKE, x0_len, FAKE, p_len, FAKE, out_len,
+                                     0.0, dt, None)
+
+
+def _desc(**kw):
+    d = dict(n=8, nsteps=100, stride=10, x0_offset=0, p_offset=0, out_offset=0, seed=1,
+             orbit_id=0)
+    d.update(kw)
+    e = abi.SodeInstance()
+    for k, v in d.items():
+        setattr(e, k, v)
+    return e
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=7), dict(n=0), dict(n=258), dict(nsteps=-1), dict(stride=0), dict(nsteps=105),
+    dict(x0_offset=995), dict(p_offset=996), dict(out_offset=10**7 - 50), dict(x0_offset=-1),
+    dict(reserved0=1), dict(reserved1=2), dict(nsteps=2**32, stride=1),
+])
+def test_ragged_rejects_bad_descriptors(bad):
+    st, h = abi.sode_create("fhn", 256, 128, 5)
+    try:
+        assert _ragged(h, [_desc(), _desc(**bad)]) == abi.SODE_EINVAL
+    finally:
+        abi.sode_destroy(h)
+
+
+def test_ragged_support_and_trivial_calls():
+    st, h = abi.sode_create("fhn", 16, 8, 5)
+    assert _ragged(h, [_desc(n=18)]) == abi.SODE_EINVAL      # above the handle's n
+    assert _ragged(h, []) == abi.SODE_OK                      # nothing to do
+    assert _ragged(h, [_desc()], dt=0.0) == abi.SODE_EINVAL
+    abi.sode_set_option(h, "precision", 64)
+    assert _ragged(h, [_desc()]) == abi.SODE_EUNSUPPORTED
+    abi.sode_destroy(h)
+    st, h = abi.sode_create("kuramoto", 4, 4, 9)
+    assert _ragged(h, [_desc()]) == abi.SODE_EUNSUPPORTED
+    for key, val in (("waves_per_cu", 8), ("units_per_lane", 4), ("graph", 0), ("persistent", 0)):
+        assert abi.sode_set_option(h, key, val) == 0
+        assert abi.sode_get_option(h, key) == (0, val)
+    assert abi.sode_set_option(h, "units_per_lane", 3) == abi.SODE_EINVAL
+    assert abi.sode_set_option(h, "waves_per_cu", 64) == abi.SODE_EINVAL
+    abi.sode_destroy(h)
