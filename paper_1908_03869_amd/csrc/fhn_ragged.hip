@@ -4,16 +4,18 @@
 //     dv_i = [v_i - v_i^3/3 - w_i + D (v_{i-1} - 2 v_i + v_{i+1})] dt + sigma dW_i
 //     dw_i = eps (v_i + a - b w_i) dt,   no-flux ends (v_0 = v_1, v_{N+1} = v_N).
 //
-// Mapping.  An instance occupies L consecutive lanes (L = 4, 8 or 16, inside
-// one DPP row) and each lane owns U consecutive units (U = 1, 2, 4 or 8),
-// L * U >= N.  A wave therefore carries 64/L instances of the same (L, U)
-// shape.  The only cross-lane data is the diffusive coupling of the two
-// units at a lane's edges: the left neighbour comes from lane l-1 by
-// row_shr:1, the right one from lane l+1 by row_shl:1.  Reads that cross an
-// instance boundary (or a row boundary) are never used: they only reach
-// units 0 and N-1, whose missing neighbour is replaced by the unit itself
-// (no-flux ends).  Units with index >= N in the last lanes are computed
-// and never stored.
+// Mapping.  An instance occupies L consecutive lanes (L = 4 .. 64) and each
+// lane owns U consecutive units (U = 1, 2, 4 or 8), L * U >= N.  A wave
+// therefore carries 64/L instances of the same (L, U) shape.  The only
+// cross-lane data is the diffusive coupling of the two units at a lane's
+// edges: the left neighbour comes from lane l-1, the right one from lane
+// l+1 -- by DPP row_shr:1 / row_shl:1 when an instance fits in a 16-lane
+// row, by ds_bpermute (__shfl_up/__shfl_down) when it spans rows.  Reads
+// that cross an instance boundary are never used: they only reach units 0
+// and N-1, whose missing neighbour is replaced by the unit itself (no-flux
+// ends).  Units with index >= N in the last lanes are computed and never
+// stored.  Long chains spread over many lanes keep the per-step dependency
+// chain short: a batch cannot finish before its longest instance.
 //
 // Precision.  Near rest the recovery variable moves by ~1e-7 per step,
 // below half a binary32 ulp of w ~ 0.6, so plain binary32 updates stall and
@@ -98,11 +100,26 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
     save(0);
     const Stream st{d.orbit_id, (uint32_t)d.seed, (uint32_t)(d.seed >> 32)};
     int64_t s = 1, next_save = d.stride;
+    // The normals do not depend on the state: those of step k+1 are drawn
+    // while step k's state update is in flight, off its dependency chain.
+    float xi_next[U];
+    if (d.nsteps > 0)
+        lane_normals<U>(st, 0u, l, xi_next);
     for (int64_t k = 0; k < d.nsteps; ++k) {
         float xi[U];
-        lane_normals<U>(st, (uint32_t)k, l, xi);
-        const float left_edge = from_lower_lane(v[U - 1]);
-        const float right_edge = from_upper_lane(v[0]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            xi[u] = xi_next[u];
+        if (k + 1 < d.nsteps)
+            lane_normals<U>(st, (uint32_t)(k + 1), l, xi_next);
+        float left_edge, right_edge;
+        if constexpr (L <= 16) {
+            left_edge = from_lower_lane(v[U - 1]);
+            right_edge = from_upper_lane(v[0]);
+        } else {
+            left_edge = __shfl_up(v[U - 1], 1, 64);
+            right_edge = __shfl_down(v[0], 1, 64);
+        }
         float dv[U], dw[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -152,6 +169,14 @@ __device__ __forceinline__ void run_shape(const RaggedKernelArgs& a, int32_t g, 
     case 9: run_group<16, 2, COMP>(a, g, lane); break;
     case 10: run_group<16, 4, COMP>(a, g, lane); break;
     case 11: run_group<16, 8, COMP>(a, g, lane); break;
+    case 12: run_group<32, 1, COMP>(a, g, lane); break;
+    case 13: run_group<32, 2, COMP>(a, g, lane); break;
+    case 14: run_group<32, 4, COMP>(a, g, lane); break;
+    case 15: run_group<32, 8, COMP>(a, g, lane); break;
+    case 16: run_group<64, 1, COMP>(a, g, lane); break;
+    case 17: run_group<64, 2, COMP>(a, g, lane); break;
+    case 18: run_group<64, 4, COMP>(a, g, lane); break;
+    case 19: run_group<64, 8, COMP>(a, g, lane); break;
     default: break;
     }
 }
@@ -197,7 +222,7 @@ __global__ void reset_counter(uint32_t* c)
 
 int ragged_shape_code(int lanes, int units)
 {
-    const int li = lanes == 4 ? 0 : lanes == 8 ? 1 : 2;
+    const int li = lanes == 4 ? 0 : lanes == 8 ? 1 : lanes == 16 ? 2 : lanes == 32 ? 3 : 4;
     const int ui = units == 1 ? 0 : units == 2 ? 1 : units == 4 ? 2 : 3;
     return li * 4 + ui;
 }

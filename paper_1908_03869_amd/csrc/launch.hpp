@@ -72,6 +72,7 @@ hipError_t launch_kuramoto_adjoint_f32(const AdjointRequest& r);
 // Ragged FitzHugh-Nagumo batches (binary32).  A group is up to
 // kRaggedSlots instances of one lane shape (L lanes x U units per lane).
 constexpr int kRaggedSlots = 16;
+constexpr int kRaggedShapes = 20;  // L in {4, 8, 16, 32, 64} x U in {1, 2, 4, 8}
 struct RaggedKernelArgs {
     const sode_instance_t* desc;  // device copy of the descriptors
     const int32_t* slots;         // [ngroups][kRaggedSlots] instance index or -1

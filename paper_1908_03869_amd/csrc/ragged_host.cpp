@@ -41,14 +41,14 @@ int pow2_at_least(int x)
 }
 
 // Lane shape of an instance with `units` chain units: U units per lane (at
-// least units_min, enough for a 16-lane row), then the fewest lanes
-// (4, 8 or 16) that hold the chain.
+// least units_min, enough for a full wave), then the fewest lanes (4 .. 64)
+// that hold the chain.
 void lane_shape(int units, int units_min, int* lanes, int* per_lane)
 {
-    int U = std::max(units_min, pow2_at_least((units + 15) / 16));
+    int U = std::max(units_min, pow2_at_least((units + 63) / 64));
     U = std::min(U, 8);
     int L = pow2_at_least((units + U - 1) / U);
-    L = std::min(std::max(L, 4), 16);
+    L = std::min(std::max(L, 4), 64);
     *lanes = L;
     *per_lane = U;
 }
@@ -88,8 +88,8 @@ void build_plan(const sode_instance_t* inst, int32_t count, int units_min, HostP
         int64_t nsteps;
         int32_t idx;
     };
-    std::vector<Member> by_shape[12];
-    int lanes_of[12] = {0}, units_of[12] = {0};
+    std::vector<Member> by_shape[kRaggedShapes];
+    int lanes_of[kRaggedShapes] = {0}, units_of[kRaggedShapes] = {0};
     for (int32_t i = 0; i < count; ++i) {
         int L, U;
         lane_shape(inst[i].n / 2, units_min, &L, &U);
@@ -105,7 +105,7 @@ void build_plan(const sode_instance_t* inst, int32_t count, int units_min, HostP
         std::vector<int32_t> members;
     };
     std::vector<Group> groups;
-    for (int code = 0; code < 12; ++code) {
+    for (int code = 0; code < kRaggedShapes; ++code) {
         auto& v = by_shape[code];
         if (v.empty())
             continue;
