@@ -147,6 +147,34 @@ def ragged_leg(sode, torch, workloads, dev, reps: int = 5) -> dict:
             "makespan_over_longest": ms / alone}
 
 
+def rnn_leg(sode, torch, workloads, dev) -> dict:
+    """The n = 256 dense-network workload (8192 orbits, 5000 steps) with each
+    matrix-product variant; MFMA work = 2 n^2 flops per orbit-step."""
+    w = workloads.rnn_dense()
+    n = w["n"]
+    X0 = torch.tensor(w["X0"], dtype=torch.float32, device=dev)
+    p = torch.tensor(w["p"], dtype=torch.float32, device=dev)
+    orbits = X0.shape[0]
+    stream = torch.cuda.current_stream()
+    res = {"workload": "rnn_dense_n256", "orbits": orbits, "nsteps": w["nsteps"]}
+    for gemm, products in (("bf16", 1), ("bf16x3", 3), ("fp32", 1)):
+        it = sode.Integrator("rnn", n, n, w["d"], precision=32, shared_params=1,
+                             kernel="matrix", gemm=gemm)
+        out = it.integrate(X0, p, 0.0, w["dt"], w["nsteps"], w["stride"], w["seed"])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        it.integrate(X0, p, 0.0, w["dt"], w["nsteps"], w["stride"], w["seed"], out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        flops = 2.0 * n * n * orbits * w["nsteps"] * products
+        res[gemm] = {"ms": ms, "orbit_steps_per_s": orbits * w["nsteps"] / (ms * 1e-3),
+                     "mfma_tflops": flops / (ms * 1e-3) / 1e12}
+        it.close()
+    return res
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +261,7 @@ def main():
 
     adj = adjoint_leg(sode, torch, workloads, dev)
     rag = ragged_leg(sode, torch, workloads, dev)
+    rnn = rnn_leg(sode, torch, workloads, dev)
 
     cpu = None
     err = None
@@ -281,6 +310,7 @@ def main():
         "error": {"max_abs_dr_final": err, "tolerance": 1e-4},
         "adjoint": adj,
         "ragged": rag,
+        "rnn": rnn,
     }
     print(json.dumps(line))
 

@@ -16,7 +16,8 @@ __all__ = ["abi", "Integrator", "SodeError", "check", "OPTION_VALUES", "Kuramoto
 OPTION_VALUES = {
     "method": {"em": 0, "rk4": 1},
     "observable": {"state": 0, "kuramoto_r": 1},
-    "kernel": {"auto": 0, "plain": 1, "coupled": 2},
+    "kernel": {"auto": 0, "plain": 1, "coupled": 2, "matrix": 3},
+    "gemm": {"bf16": 0, "bf16x3": 1, "fp32": 2},
 }
 
 
@@ -34,7 +35,7 @@ class Integrator:
         self.model, self.n, self.m, self.d = model, n, m, d
         self.options = {"precision": 32, "method": 0, "observable": 0, "kernel": 0,
                         "shared_params": 0, "compensated": 1, "waves_per_cu": 0,
-                        "units_per_lane": 0, "graph": 1, "persistent": 1}
+                        "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1}
         for k, v in options.items():
             self.set_option(k, v)
 

@@ -19,7 +19,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsode.so")
 
 SOURCES = ["sode_abi.cpp", "ragged_host.cpp", "plain.hip", "kuramoto_coupled.hip",
-           "kuramoto_adjoint.hip", "fhn_ragged.hip"]
+           "kuramoto_adjoint.hip", "fhn_ragged.hip", "rnn_mfma.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I" + INCLUDE, "-I" + CSRC,

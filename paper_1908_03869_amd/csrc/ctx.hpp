@@ -15,9 +15,10 @@ struct sode_ctx {
     int precision = 32;
     int method = sode::kEM;
     int observable = sode::kState;
-    int kernel = 0;  // 0 auto, 1 plain, 2 coupled
+    int kernel = 0;  // 0 auto, 1 plain, 2 coupled, 3 matrix (dense network)
     int shared_params = 0;
     int compensated = 1;
+    int gemm = sode::kRnnBf16x3;  // dense-network matrix product variant
     // Ragged batches: 0 = autotuned.
     int waves_per_cu = 0;
     int units_per_lane = 0;

@@ -69,6 +69,12 @@ struct AdjointRequest {
 hipError_t launch_kuramoto_forward_ckpt_f32(const AdjointRequest& r);
 hipError_t launch_kuramoto_adjoint_f32(const AdjointRequest& r);
 
+// Dense random networks with the drift's matrix product on MFMA (binary32
+// state, shared parameters, n in {64, 128, 256}).
+enum RnnGemm : int { kRnnBf16 = 0, kRnnBf16x3 = 1, kRnnFp32 = 2 };
+bool rnn_mfma_supports(int n);
+hipError_t launch_rnn_mfma_f32(const Request& r, int mode);
+
 // Ragged FitzHugh-Nagumo batches (binary32).  A group is up to
 // kRaggedSlots instances of one lane shape (L lanes x U units per lane).
 constexpr int kRaggedSlots = 16;

@@ -98,8 +98,14 @@ int choose_kernel(const sode_ctx* h, int* kernel)
 {
     const bool coupled_ok = h->model == sode::kKuramoto && h->precision == 32 &&
                             h->method == sode::kEM && sode::coupled_supports(h->n);
+    const bool matrix_ok = h->model == sode::kRNN && h->precision == 32 && h->method == sode::kEM &&
+                           h->shared_params && sode::rnn_mfma_supports(h->n);
     const bool plain_ok = h->n <= sode::kPlainMaxN;
-    if (h->kernel == 2) {
+    if (h->kernel == 3) {
+        if (!matrix_ok)
+            return SODE_EUNSUPPORTED;
+        *kernel = 3;
+    } else if (h->kernel == 2) {
         if (!coupled_ok)
             return SODE_EUNSUPPORTED;
         *kernel = 2;
@@ -109,6 +115,8 @@ int choose_kernel(const sode_ctx* h, int* kernel)
         *kernel = 1;
     } else if (coupled_ok) {
         *kernel = 2;
+    } else if (matrix_ok) {
+        *kernel = 3;
     } else if (plain_ok) {
         *kernel = 1;
     } else {
@@ -177,9 +185,13 @@ int sode_set_option(sode_t h, const char* key, int64_t value)
             return SODE_EINVAL;
         h->observable = (int)value;
     } else if (std::strcmp(key, "kernel") == 0) {
-        if (value < 0 || value > 2)
+        if (value < 0 || value > 3)
             return SODE_EINVAL;
         h->kernel = (int)value;
+    } else if (std::strcmp(key, "gemm") == 0) {
+        if (value != sode::kRnnBf16 && value != sode::kRnnBf16x3 && value != sode::kRnnFp32)
+            return SODE_EINVAL;
+        h->gemm = (int)value;
     } else if (std::strcmp(key, "shared_params") == 0) {
         if (value != 0 && value != 1)
             return SODE_EINVAL;
@@ -222,6 +234,8 @@ int sode_get_option(sode_t h, const char* key, int64_t* value)
         *value = h->observable;
     else if (std::strcmp(key, "kernel") == 0)
         *value = h->kernel;
+    else if (std::strcmp(key, "gemm") == 0)
+        *value = h->gemm;
     else if (std::strcmp(key, "shared_params") == 0)
         *value = h->shared_params;
     else if (std::strcmp(key, "compensated") == 0)
@@ -298,7 +312,9 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
     r.stream = static_cast<hipStream_t>(stream);
 
     hipError_t e;
-    if (kernel == 2)
+    if (kernel == 3)
+        e = sode::launch_rnn_mfma_f32(r, h->gemm);
+    else if (kernel == 2)
         e = sode::launch_kuramoto_coupled_f32(r);
     else if (h->precision == 64)
         e = sode::launch_plain_f64(r);

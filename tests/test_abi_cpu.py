@@ -130,6 +130,17 @@ def test_unsupported_kernel_requests():
     st, h = abi.sode_create("ou", 200, 200, 3)  # beyond the plain kernel's 128 states
     assert _call(h) == abi.SODE_EUNSUPPORTED
     abi.sode_destroy(h)
+    st, h = abi.sode_create("rnn", 256, 256, 256 * 256 + 257)
+    assert _call(h) == abi.SODE_EUNSUPPORTED  # n = 256 needs the matrix kernel: shared W
+    abi.sode_set_option(h, "shared_params", 1)
+    abi.sode_set_option(h, "kernel", 3)
+    abi.sode_set_option(h, "observable", 0)
+    abi.sode_set_option(h, "precision", 64)
+    assert _call(h) == abi.SODE_EUNSUPPORTED  # matrix kernel is binary32
+    assert abi.sode_set_option(h, "gemm", 3) == abi.SODE_EINVAL
+    for g in (0, 1, 2):
+        assert abi.sode_set_option(h, "gemm", g) == 0 and abi.sode_get_option(h, "gemm") == (0, g)
+    abi.sode_destroy(h)
 
 
 def test_python_layer_raises_on_error():
