@@ -100,6 +100,10 @@ int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out)
  *                  orbit exchange phases through DPP row rotations).
  *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
  *                  used by every orbit.
+ *   "drift"        Kuramoto coupling sum: 0 = pairwise sines as in Fig. 5
+ *                  (default); 1 = the exactly equivalent mean-field form
+ *                  cos(theta_i) sum_j sin(theta_j) - sin(theta_i) sum_j
+ *                  cos(theta_j), O(n) per orbit-step (all Kuramoto paths).
  *   "compensated"  binary32 Kuramoto kernels (coupled, forward_ckpt,
  *                  adjoint) and the ragged FHN kernel: 1 (default) carries
  *                  each state variable as hi + lo and adds every increment
@@ -223,6 +227,23 @@ int sode_adjoint(sode_t h, const void* p, int64_t orbits, double t0, double dt, 
 int sode_integrate_ragged(sode_t h, const sode_instance_t* inst, int32_t count, const void* X0,
                           int64_t x0_len, const void* p, int64_t p_len, void* out,
                           int64_t out_len, double t0, double dt, void* stream);
+
+/*
+ * sode_ensemble_stats - mean and standard deviation over orbits of every
+ * column of a saved-observable array, in binary64: the ensemble statistics
+ * <r(t)> and sigma(r(t)) of the accuracy study (Sec. 2.3.1-2.3.2).
+ *
+ *   out     [orbits][cols] DEVICE array of the handle's precision (cols =
+ *           nsave * q for the output of sode_integrate).
+ *   mean    [cols] double;  stddev [cols] double or NULL: sample standard
+ *           deviation (denominator orbits - 1; 0 when orbits < 2).
+ * The reduction order is fixed (64 orbit chunks merged in order), so the
+ * result is reproducible bit for bit.  Uses the handle's scratch area
+ * (64 * cols * 24 bytes; growing it may allocate).  With orbits = 0 the
+ * means are 0.
+ */
+int sode_ensemble_stats(sode_t h, const void* out, int64_t orbits, int64_t cols, double* mean,
+                        double* stddev, void* stream);
 
 /*
  * sode_sync - wait for the handle's last launch and report device errors.

@@ -18,6 +18,7 @@ OPTION_VALUES = {
     "observable": {"state": 0, "kuramoto_r": 1},
     "kernel": {"auto": 0, "plain": 1, "coupled": 2, "matrix": 3},
     "gemm": {"bf16": 0, "bf16x3": 1, "fp32": 2},
+    "drift": {"pairwise": 0, "meanfield": 1},
 }
 
 
@@ -35,7 +36,7 @@ class Integrator:
         self.model, self.n, self.m, self.d = model, n, m, d
         self.options = {"precision": 32, "method": 0, "observable": 0, "kernel": 0,
                         "shared_params": 0, "compensated": 1, "waves_per_cu": 0,
-                        "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1}
+                        "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1, "drift": 0}
         for k, v in options.items():
             self.set_option(k, v)
 
@@ -143,6 +144,22 @@ class Integrator:
                                        out.numel(), t0, dt, stream)
         check(st, "sode_integrate_ragged")
         return out
+
+    def ensemble_stats(self, out, stream=None):
+        """sode_ensemble_stats over out[orbits, ...]: (mean, std) float64 of shape out[0]."""
+        import torch
+        orbits = out.shape[0]
+        cols = out[0].numel() if orbits > 0 else 0
+        if out.dtype != self.dtype or not out.is_contiguous():
+            raise ValueError("out must be contiguous in the handle's precision")
+        mean = torch.empty(out.shape[1:], dtype=torch.float64, device=out.device)
+        std = torch.empty(out.shape[1:], dtype=torch.float64, device=out.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(out.device).cuda_stream
+        st = abi.sode_ensemble_stats(self.handle, out.data_ptr(), orbits, cols, mean.data_ptr(),
+                                     std.data_ptr(), stream)
+        check(st, "sode_ensemble_stats")
+        return mean, std
 
     def get_option(self, key: str) -> int:
         st, v = abi.sode_get_option(self.handle, key)

@@ -24,7 +24,7 @@ SODE_ENONFINITE = -5
 EXPORTS = (
     "sode_create", "sode_set_option", "sode_get_option", "sode_integrate",
     "sode_integrate_ex", "sode_forward_ckpt", "sode_adjoint", "sode_integrate_ragged",
-    "sode_sync", "sode_destroy", "sode_strerror", "sode_version",
+    "sode_ensemble_stats", "sode_sync", "sode_destroy", "sode_strerror", "sode_version",
 )
 
 
@@ -80,6 +80,8 @@ def load() -> ctypes.CDLL:
     L.sode_integrate_ragged.argtypes = [vp, ctypes.POINTER(SodeInstance), ctypes.c_int32, vp, i64,
                                         vp, i64, vp, i64, f64, f64, vp]
     L.sode_integrate_ragged.restype = ctypes.c_int
+    L.sode_ensemble_stats.argtypes = [vp, vp, i64, i64, vp, vp, vp]
+    L.sode_ensemble_stats.restype = ctypes.c_int
     L.sode_sync.argtypes = [vp]
     L.sode_sync.restype = ctypes.c_int
     L.sode_destroy.argtypes = [vp]
@@ -137,6 +139,10 @@ def sode_integrate_ragged(h, inst, count, X0, x0_len, p, p_len, out, out_len, t0
                           stream) -> int:
     return load().sode_integrate_ragged(h, inst, count, X0, x0_len, p, p_len, out, out_len, t0,
                                         dt, stream)
+
+
+def sode_ensemble_stats(h, out, orbits, cols, mean, stddev, stream) -> int:
+    return load().sode_ensemble_stats(h, out, orbits, cols, mean, stddev, stream)
 
 
 def sode_sync(h) -> int:

@@ -19,7 +19,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsode.so")
 
 SOURCES = ["sode_abi.cpp", "ragged_host.cpp", "plain.hip", "kuramoto_coupled.hip",
-           "kuramoto_adjoint.hip", "fhn_ragged.hip", "rnn_mfma.hip"]
+           "kuramoto_adjoint.hip", "fhn_ragged.hip", "rnn_mfma.hip",
+           "stats.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I" + INCLUDE, "-I" + CSRC,

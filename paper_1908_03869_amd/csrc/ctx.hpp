@@ -18,6 +18,7 @@ struct sode_ctx {
     int kernel = 0;  // 0 auto, 1 plain, 2 coupled, 3 matrix (dense network)
     int shared_params = 0;
     int compensated = 1;
+    int drift = 0;  // Kuramoto coupling: 0 pairwise sines, 1 mean-field identity
     int gemm = sode::kRnnBf16x3;  // dense-network matrix product variant
     // Ragged batches: 0 = autotuned.
     int waves_per_cu = 0;

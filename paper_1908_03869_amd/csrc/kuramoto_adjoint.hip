@@ -67,7 +67,7 @@ struct AdjointArgs {
 
 __device__ __forceinline__ bool in_window(int64_t k, int64_t lo, int64_t hi) { return k >= lo && k <= hi; }
 
-template <int N, bool COMP>
+template <int N, bool COMP, bool MF>
 __global__ __launch_bounds__(256) void forward_ckpt_kernel(const CkptArgs a)
 {
     constexpr int P = N / 16;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void forward_ckpt_kernel(const CkptArgs a)
     int64_t k = 0;
     for (int64_t cidx = 1; cidx < a.nckpt; ++cidx) {
         for (int64_t kk = 0; kk < a.every; ++kk, ++k) {
-            em_step<P, COMP>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)k), l);
+            em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)k), l);
             if (in_window(k + 1, a.win_lo, a.win_hi))
                 racc += (double)order_parameter<P>(th);
         }
@@ -128,7 +128,7 @@ __device__ __forceinline__ double row_sum_f64(double v)
     return v;
 }
 
-template <int N, bool COMP>
+template <int N, bool COMP, bool MF>
 __global__ __launch_bounds__(256) void adjoint_kernel(const AdjointArgs a)
 {
     constexpr int P = N / 16;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjointArgs a)
             for (int i = 0; i < P; ++i)
                 seg[j * 16 * P + i] = th[i];
             if (j + 1 < a.every)
-                em_step<P, COMP>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)(kbase + j)), l);
+                em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)(kbase + j)), l);
         }
         // Reverse sweep over the segment.
         for (int64_t j = a.every - 1; j >= 0; --j) {
@@ -262,10 +262,15 @@ hipError_t launch_ckpt_n(const AdjointRequest& r)
     a.orbit_offset = r.orbit_offset;
     a.step_offset = r.step_offset;
     const dim3 grid((unsigned)((r.orbits * 16 + 255) / 256));
-    if (r.compensated)
-        hipLaunchKernelGGL((forward_ckpt_kernel<N, true>), grid, dim3(256), 0, r.stream, a);
+    const bool mf = r.drift == 1;
+    if (r.compensated && mf)
+        hipLaunchKernelGGL((forward_ckpt_kernel<N, true, true>), grid, dim3(256), 0, r.stream, a);
+    else if (r.compensated)
+        hipLaunchKernelGGL((forward_ckpt_kernel<N, true, false>), grid, dim3(256), 0, r.stream, a);
+    else if (mf)
+        hipLaunchKernelGGL((forward_ckpt_kernel<N, false, true>), grid, dim3(256), 0, r.stream, a);
     else
-        hipLaunchKernelGGL((forward_ckpt_kernel<N, false>), grid, dim3(256), 0, r.stream, a);
+        hipLaunchKernelGGL((forward_ckpt_kernel<N, false, false>), grid, dim3(256), 0, r.stream, a);
     return hipGetLastError();
 }
 
@@ -295,10 +300,15 @@ hipError_t launch_adjoint_n(const AdjointRequest& r)
     a.step_offset = r.step_offset;
     if (r.orbits > 0) {
         const dim3 grid((unsigned)((r.orbits * 16 + 255) / 256));
-        if (r.compensated)
-            hipLaunchKernelGGL((adjoint_kernel<N, true>), grid, dim3(256), 0, r.stream, a);
+        const bool mf = r.drift == 1;
+        if (r.compensated && mf)
+            hipLaunchKernelGGL((adjoint_kernel<N, true, true>), grid, dim3(256), 0, r.stream, a);
+        else if (r.compensated)
+            hipLaunchKernelGGL((adjoint_kernel<N, true, false>), grid, dim3(256), 0, r.stream, a);
+        else if (mf)
+            hipLaunchKernelGGL((adjoint_kernel<N, false, true>), grid, dim3(256), 0, r.stream, a);
         else
-            hipLaunchKernelGGL((adjoint_kernel<N, false>), grid, dim3(256), 0, r.stream, a);
+            hipLaunchKernelGGL((adjoint_kernel<N, false, false>), grid, dim3(256), 0, r.stream, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;

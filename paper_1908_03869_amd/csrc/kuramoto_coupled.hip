@@ -1,8 +1,9 @@
 // kuramoto_coupled.hip - binary32 Euler-Maruyama integration of stochastic
 // Kuramoto networks (Eq. 5/6 of Sec. 2.2.1) with all-to-all sine coupling,
 // one orbit per 16-lane DPP row (the lane mapping and the pair evaluation
-// are described in kuramoto_lanes.hpp).  Saves the state or the order
-// parameter every `stride` steps (Sec. 2.1.4).
+// are described in kuramoto_lanes.hpp), pairwise or through the mean-field
+// identity.  Saves the state or the order parameter every `stride` steps
+// (Sec. 2.1.4).
 #include "kuramoto_lanes.hpp"
 #include "launch.hpp"
 
@@ -17,7 +18,7 @@ struct CoupledArgs {
     float* __restrict__ out;
     const uint32_t* __restrict__ ids;
     const uint64_t* __restrict__ seeds;
-    int p_per_orbit, observable, compensated;
+    int p_per_orbit, observable, compensated, drift;
     int64_t orbits, stride, nsave;
     float dt, sqdt, dt_over_n;
     uint64_t seed, orbit_offset, step_offset;
@@ -38,7 +39,7 @@ __device__ __forceinline__ void save(const CoupledArgs& a, int l, const float (&
     }
 }
 
-template <int N, bool COMP>
+template <int N, bool COMP, bool MF>
 __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs a)
 {
     constexpr int P = N / 16;
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs
     uint32_t k = (uint32_t)a.step_offset;
     for (int64_t s = 1; s < a.nsave; ++s) {
         for (int64_t kk = 0; kk < a.stride; ++kk, ++k)
-            em_step<P, COMP>(th, tl, c, st, k, l);
+            em_step<P, COMP, MF>(th, tl, c, st, k, l);
         save<P>(a, l, th, out_row, s);
     }
 }
@@ -94,10 +95,17 @@ hipError_t launch_n(const Request& r)
     const int64_t threads = r.orbits * 16;
     const dim3 block(256);
     const dim3 grid((unsigned)((threads + 255) / 256));
-    if (r.compensated)
-        hipLaunchKernelGGL((kuramoto_coupled_kernel<N, true>), grid, block, 0, r.stream, a);
-    else
-        hipLaunchKernelGGL((kuramoto_coupled_kernel<N, false>), grid, block, 0, r.stream, a);
+    if (r.drift == 1) {
+        if (r.compensated)
+            hipLaunchKernelGGL((kuramoto_coupled_kernel<N, true, true>), grid, block, 0, r.stream, a);
+        else
+            hipLaunchKernelGGL((kuramoto_coupled_kernel<N, false, true>), grid, block, 0, r.stream, a);
+    } else {
+        if (r.compensated)
+            hipLaunchKernelGGL((kuramoto_coupled_kernel<N, true, false>), grid, block, 0, r.stream, a);
+        else
+            hipLaunchKernelGGL((kuramoto_coupled_kernel<N, false, false>), grid, block, 0, r.stream, a);
+    }
     return hipGetLastError();
 }
 

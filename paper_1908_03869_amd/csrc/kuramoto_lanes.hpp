@@ -169,12 +169,33 @@ __device__ __forceinline__ LaneCoefficients<P> lane_coefficients(const float* __
 // taken as is, so a saved state passed back in continues bit-exactly.
 __device__ __forceinline__ float load_phase(float x) { return __builtin_fabsf(x) <= kPiF ? x : wrap_rad(x); }
 
+// Coupling sums through the angle-difference identity:
+// sum_j sin(theta_j - theta_i) = cos(theta_i) S - sin(theta_i) C with the row
+// sums C = sum cos, S = sum sin -- O(N) per orbit instead of N(N-1)/2 sines.
+template <int P>
+__device__ __forceinline__ void mean_field_sums(const float (&phi)[P], float (&acc)[P])
+{
+    float cs[P], sn[P], c = 0.0f, s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        cs[i] = cos_rev(phi[i]);
+        sn[i] = sin_rev(phi[i]);
+        c += cs[i];
+        s += sn[i];
+    }
+    const float C = row_sum(c), S = row_sum(s);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        acc[i] = cs[i] * S - sn[i] * C;
+}
+
 // One Euler-Maruyama step (Eq. 6) of the lane's P oscillators at global
 // step k: theta += omega dt + (K/N) S dt + p sqrt(dt) xi, then wrap.
 // COMP: th is the leading part of hi + lo and tl the trailing part; the
 // increment and the old trailing part are added with an error-free two-sum,
-// and a wrap moves the tail of 2 pi into tl.
-template <int P, bool COMP>
+// and a wrap moves the tail of 2 pi into tl.  MF: coupling through the
+// mean-field identity instead of pairwise sines.
+template <int P, bool COMP, bool MF = false>
 __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const LaneCoefficients<P>& c,
                                         const Stream& st, uint32_t k, int l)
 {
@@ -182,7 +203,10 @@ __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const La
 #pragma unroll
     for (int i = 0; i < P; ++i)
         phi[i] = th[i] * kInvTwoPi;
-    coupling_sums<P>(phi, acc);
+    if constexpr (MF)
+        mean_field_sums<P>(phi, acc);
+    else
+        coupling_sums<P>(phi, acc);
     lane_normals<P>(st, k, l, xi);
 #pragma unroll
     for (int i = 0; i < P; ++i) {

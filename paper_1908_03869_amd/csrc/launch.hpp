@@ -30,6 +30,7 @@ struct Request {
     int method;
     int observable;
     int compensated;  // binary32 coupled kernels: two-sum compensated state
+    int drift;        // Kuramoto coupling sum: 0 pairwise, 1 mean-field identity
     void* out;  // [orbits][nsave][q]
     hipStream_t stream;
 };
@@ -54,6 +55,7 @@ struct AdjointRequest {
     const void* p;         // [orbits][d] or [d]
     int p_per_orbit;
     int compensated;
+    int drift;
     int64_t orbits;
     double dt;
     int64_t nsteps, every, win_lo, win_hi;
@@ -68,6 +70,20 @@ struct AdjointRequest {
 };
 hipError_t launch_kuramoto_forward_ckpt_f32(const AdjointRequest& r);
 hipError_t launch_kuramoto_adjoint_f32(const AdjointRequest& r);
+
+// Ensemble statistics over orbits of a saved-observable array (binary64).
+struct StatsRequest {
+    const void* x;   // [orbits][cols] of the given precision
+    int precision;   // 32 or 64
+    int64_t orbits, cols;
+    int64_t groups, chunk;  // orbit chunks of the first pass
+    void* scratch;          // groups * cols partials
+    double* mean;           // [cols]
+    double* stddev;         // [cols] or null
+    hipStream_t stream;
+};
+size_t stats_partial_bytes();
+hipError_t launch_ensemble_stats(const StatsRequest& r);
 
 // Dense random networks with the drift's matrix product on MFMA (binary32
 // state, shared parameters, n in {64, 128, 256}).

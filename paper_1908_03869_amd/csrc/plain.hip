@@ -149,9 +149,22 @@ hipError_t launch_plain(const Request& r)
 {
     switch (r.model) {
     case kKuramoto:
-        if (r.n == 4)
-            return launch_one<Kuramoto, R, 4>(r);
-        return launch_one<Kuramoto, R, 0>(r);
+        if (r.drift == 1) {
+            switch (r.n) {
+            case 4: return launch_one<KuramotoMeanField, R, 4>(r);
+            case 5: return launch_one<KuramotoMeanField, R, 5>(r);
+            case 10: return launch_one<KuramotoMeanField, R, 10>(r);
+            case 15: return launch_one<KuramotoMeanField, R, 15>(r);
+            default: return launch_one<KuramotoMeanField, R, 0>(r);
+            }
+        }
+        switch (r.n) {
+        case 4: return launch_one<Kuramoto, R, 4>(r);
+        case 5: return launch_one<Kuramoto, R, 5>(r);
+        case 10: return launch_one<Kuramoto, R, 10>(r);
+        case 15: return launch_one<Kuramoto, R, 15>(r);
+        default: return launch_one<Kuramoto, R, 0>(r);
+        }
     case kOU:
         if (r.n == 1)
             return launch_one<OrnsteinUhlenbeck, R, 1>(r);

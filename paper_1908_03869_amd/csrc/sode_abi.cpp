@@ -200,6 +200,10 @@ int sode_set_option(sode_t h, const char* key, int64_t value)
         if (value != 0 && value != 1)
             return SODE_EINVAL;
         h->compensated = (int)value;
+    } else if (std::strcmp(key, "drift") == 0) {
+        if (value != 0 && value != 1)
+            return SODE_EINVAL;
+        h->drift = (int)value;
     } else if (std::strcmp(key, "waves_per_cu") == 0) {
         if (value < 0 || value > 32)
             return SODE_EINVAL;
@@ -240,6 +244,8 @@ int sode_get_option(sode_t h, const char* key, int64_t* value)
         *value = h->shared_params;
     else if (std::strcmp(key, "compensated") == 0)
         *value = h->compensated;
+    else if (std::strcmp(key, "drift") == 0)
+        *value = h->drift;
     else if (std::strcmp(key, "waves_per_cu") == 0)
         *value = h->waves_per_cu;
     else if (std::strcmp(key, "units_per_lane") == 0)
@@ -308,6 +314,7 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
     r.method = h->method;
     r.observable = h->observable;
     r.compensated = h->compensated;
+    r.drift = h->drift;
     r.out = out;
     r.stream = static_cast<hipStream_t>(stream);
 
@@ -366,6 +373,7 @@ int sode_forward_ckpt(sode_t h, const void* X0, const void* p, int64_t orbits, d
     r.p = p;
     r.p_per_orbit = h->shared_params ? 0 : 1;
     r.compensated = h->compensated;
+    r.drift = h->drift;
     r.orbits = orbits;
     r.dt = dt;
     r.nsteps = nsteps;
@@ -411,6 +419,7 @@ int sode_adjoint(sode_t h, const void* p, int64_t orbits, double t0, double dt, 
     r.p = p;
     r.p_per_orbit = h->shared_params ? 0 : 1;
     r.compensated = h->compensated;
+    r.drift = h->drift;
     r.orbits = orbits;
     r.dt = dt;
     r.nsteps = nsteps;
@@ -429,6 +438,43 @@ int sode_adjoint(sode_t h, const void* p, int64_t orbits, double t0, double dt, 
     r.seg_scratch = static_cast<float*>(h->scratch);
     r.stream = static_cast<hipStream_t>(stream);
     const hipError_t e = sode::launch_kuramoto_adjoint_f32(r);
+    h->last_error = e;
+    h->last_stream = r.stream;
+    h->launched = true;
+    return status_of(e);
+}
+
+int sode_ensemble_stats(sode_t h, const void* out, int64_t orbits, int64_t cols, double* mean,
+                        double* stddev, void* stream)
+{
+    if (!h || orbits < 0 || cols < 0)
+        return SODE_EINVAL;
+    if (cols == 0)
+        return SODE_OK;
+    if (!mean || (orbits > 0 && !out))
+        return SODE_EINVAL;
+    if (orbits > 0 && cols > INT64_MAX / 16 / orbits)
+        return SODE_EINVAL;
+    if ((cols + 255) / 256 > INT32_MAX)
+        return SODE_EINVAL;
+    sode::StatsRequest r{};
+    r.x = out;
+    r.precision = h->precision;
+    r.orbits = orbits;
+    r.cols = cols;
+    // About 64 orbit chunks, fewer for small ensembles.
+    r.groups = orbits < 64 ? (orbits > 0 ? orbits : 1) : 64;
+    r.chunk = orbits > 0 ? (orbits + r.groups - 1) / r.groups : 1;
+    r.groups = orbits > 0 ? (orbits + r.chunk - 1) / r.chunk : 1;
+    const size_t need = (size_t)r.groups * (size_t)cols * sode::stats_partial_bytes();
+    const int sc = ensure_scratch(h, need);
+    if (sc != SODE_OK)
+        return sc;
+    r.scratch = h->scratch;
+    r.mean = mean;
+    r.stddev = stddev;
+    r.stream = static_cast<hipStream_t>(stream);
+    const hipError_t e = sode::launch_ensemble_stats(r);
     h->last_error = e;
     h->last_stream = r.stream;
     h->launched = true;

@@ -65,12 +65,13 @@ def test_options_round_trip_and_reject_unknown():
     assert st == 0
     try:
         for key, val in (("precision", 64), ("method", 1), ("observable", 1), ("kernel", 2),
-                         ("shared_params", 1)):
+                         ("shared_params", 1), ("drift", 1)):
             assert abi.sode_set_option(h, key, val) == 0
             assert abi.sode_get_option(h, key) == (0, val)
         assert abi.sode_set_option(h, "precision", 16) == abi.SODE_EINVAL
         assert abi.sode_set_option(h, "method", 2) == abi.SODE_EINVAL
         assert abi.sode_set_option(h, "kernel", 7) == abi.SODE_EINVAL
+        assert abi.sode_set_option(h, "drift", 2) == abi.SODE_EINVAL
         assert abi.sode_set_option(h, "bogus", 1) == abi.SODE_EINVAL
         assert abi.sode_get_option(h, "bogus")[0] == abi.SODE_EINVAL
         assert abi.sode_get_option(h, "precision") == (0, 64)
@@ -250,4 +251,15 @@ def test_ragged_support_and_trivial_calls():
         assert abi.sode_get_option(h, key) == (0, val)
     assert abi.sode_set_option(h, "units_per_lane", 3) == abi.SODE_EINVAL
     assert abi.sode_set_option(h, "waves_per_cu", 64) == abi.SODE_EINVAL
+    abi.sode_destroy(h)
+
+
+def test_ensemble_stats_argument_checks():
+    st, h = abi.sode_create("kuramoto", 4, 4, 9)
+    assert abi.sode_ensemble_stats(h, FAKE, -1, 10, FAKE, None, None) == abi.SODE_EINVAL
+    assert abi.sode_ensemble_stats(h, FAKE, 10, -1, FAKE, None, None) == abi.SODE_EINVAL
+    assert abi.sode_ensemble_stats(h, None, 10, 10, FAKE, None, None) == abi.SODE_EINVAL
+    assert abi.sode_ensemble_stats(h, FAKE, 10, 10, None, None, None) == abi.SODE_EINVAL
+    assert abi.sode_ensemble_stats(h, FAKE, 10, 0, None, None, None) == abi.SODE_OK
+    assert abi.sode_ensemble_stats(None, FAKE, 10, 10, FAKE, None, None) == abi.SODE_EINVAL
     abi.sode_destroy(h)
