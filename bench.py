@@ -10,7 +10,10 @@ Printed JSON line (rank 0): the driver's contract fields plus
   roofline      the coupled kernel against the VALU issue roofline,
   cpu_baseline  the FP64 oracle timed on a bounded sample on the host,
   plain_fp64    the one-orbit-per-lane FP64 kernel on the same ensemble,
-  error         max |dr| against the oracle on the sampled orbits.
+  error         max |dr| against the oracle on the sampled orbits,
+  meanfield     the same ensemble with the O(n) mean-field drift form,
+and the adjoint, ragged-batch and dense-network legs.  --paper-sweep REPS
+prints the Sec. 2.2.1 speed protocol instead (one line per case).
 """
 from __future__ import annotations
 
@@ -175,6 +178,62 @@ def rnn_leg(sode, torch, workloads, dev) -> dict:
     return res
 
 
+PAPER_N = (5, 10, 15)
+PAPER_M = (512, 5120, 25600, 40960, 81920, 163840)
+
+
+def paper_sweep(sode, torch, workloads, dev, reps: int) -> None:
+    """The speed protocol of Sec. 2.2.1 (Tables S1-S3): Kuramoto N in
+    {5, 10, 15}, M orbits from 512 to 163,840, K = 1, 8000 Euler-Maruyama
+    steps of 0.05 s, in binary64 and binary32, with the pairwise and the
+    mean-field drift.  One JSON line per case: the kernel time with inputs
+    resident in HBM and the host-to-host time (upload of X0 and p, the
+    integration, download of the saved states), each the median of `reps`
+    runs after one warm-up."""
+    for prec in (64, 32):
+        dtype = torch.float64 if prec == 64 else torch.float32
+        for N in PAPER_N:
+            for drift in ("pairwise", "meanfield"):
+                it = sode.Integrator("kuramoto", N, N, 2 * N + 1, precision=prec,
+                                     kernel="plain", drift=drift)
+                for M in PAPER_M:
+                    w = workloads.kuramoto_paper(N, M)
+                    X0h = torch.tensor(w["X0"], dtype=dtype).pin_memory()
+                    ph = torch.tensor(w["p"], dtype=dtype).pin_memory()
+                    nsave = w["nsteps"] // w["stride"] + 1
+                    outh = torch.empty((M, nsave, N), dtype=dtype).pin_memory()
+                    X0 = X0h.to(dev)
+                    p = ph.to(dev)
+                    out = torch.empty((M, nsave, N), dtype=dtype, device=dev)
+                    args = (0.0, w["dt"], w["nsteps"], w["stride"], w["seed"])
+                    stream = torch.cuda.current_stream()
+                    it.integrate(X0, p, *args, out=out)
+                    torch.cuda.synchronize()
+                    kern, host = [], []
+                    for _ in range(reps):
+                        e0 = torch.cuda.Event(enable_timing=True)
+                        e1 = torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        it.integrate(X0, p, *args, out=out)
+                        e1.record(stream)
+                        torch.cuda.synchronize()
+                        kern.append(e0.elapsed_time(e1))
+                        h0 = time.perf_counter()
+                        X0.copy_(X0h, non_blocking=True)
+                        p.copy_(ph, non_blocking=True)
+                        it.integrate(X0, p, *args, out=out)
+                        outh.copy_(out, non_blocking=True)
+                        torch.cuda.synchronize()
+                        host.append((time.perf_counter() - h0) * 1e3)
+                    k_ms, h_ms = float(np.median(kern)), float(np.median(host))
+                    print(json.dumps({
+                        "sweep": "paper_kuramoto", "precision": prec, "N": N, "M": M,
+                        "drift": drift, "nsteps": w["nsteps"], "stride": w["stride"],
+                        "kernel_ms": k_ms, "host_ms": h_ms,
+                        "orbit_steps_per_s": M * w["nsteps"] / (k_ms * 1e-3)}), flush=True)
+                it.close()
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +244,9 @@ def parse():
     ap.add_argument("--cpu-orbits", type=int, default=4,
                     help="orbits of the oracle sample (full 2x10^4 steps each)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--paper-sweep", type=int, default=0, metavar="REPS",
+                    help="instead of the benchmark line, time the Sec. 2.2.1 speed protocol "
+                         "(N x M x precision x drift form), REPS runs per case")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB, so that "
                          "HBM byte counters can be scaled against a kernel of known traffic")
@@ -204,6 +266,9 @@ def main():
     import paper_1908_03869_amd as sode
 
     dev = torch.device("cuda:0")
+    if args.paper_sweep:
+        paper_sweep(sode, torch, workloads, dev, args.paper_sweep)
+        return
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -259,12 +324,28 @@ def main():
     plain_ms = b0.elapsed_time(b1)
     plain_rate = orbits * bsteps / (plain_ms * 1e-3)
 
+    # The same ensemble with the O(n) mean-field form of the coupling.
+    itmf = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, observable="kuramoto_r",
+                           drift="meanfield")
+    outmf = torch.empty_like(out)
+    itmf.integrate(X0, p, 0.0, w["dt"], nsteps, stride, w["seed"], out=outmf)
+    torch.cuda.synchronize()
+    m0 = torch.cuda.Event(enable_timing=True)
+    m1 = torch.cuda.Event(enable_timing=True)
+    m0.record(stream)
+    itmf.integrate(X0, p, 0.0, w["dt"], nsteps, stride, w["seed"], out=outmf)
+    m1.record(stream)
+    torch.cuda.synchronize()
+    mf_ms = m0.elapsed_time(m1)
+    r_mf = outmf[:, -1, 0].double().cpu().numpy()
+    itmf.close()
+
     adj = adjoint_leg(sode, torch, workloads, dev)
     rag = ragged_leg(sode, torch, workloads, dev)
     rnn = rnn_leg(sode, torch, workloads, dev)
 
     cpu = None
-    err = None
+    err = err_mf = None
     if not args.no_cpu:
         import oracle
         rows = w["diagonal"][np.linspace(0, 255, args.cpu_orbits).astype(int)]
@@ -281,6 +362,7 @@ def main():
                "sample": f"{len(rows)} grid-diagonal orbits x {nsteps} steps, FP64, "
                          f"single-threaded, {cpu_s:.1f} s"}
         err = float(np.max(np.abs(r_gpu[rows] - ref[:, -1, 0])))
+        err_mf = float(np.max(np.abs(r_mf[rows] - ref[:, -1, 0])))
 
     line = {
         "metric": "orbit*steps/s (Kuramoto n=64 FP32 Euler-Maruyama ensemble)",
@@ -308,6 +390,8 @@ def main():
         "plain_fp64": {"value": plain_rate, "unit": "orbit*steps/s", "nsteps": bsteps,
                        "speedup_of_value": value / plain_rate},
         "error": {"max_abs_dr_final": err, "tolerance": 1e-4},
+        "meanfield": {"value": orbits * nsteps / (mf_ms * 1e-3), "unit": "orbit*steps/s",
+                      "kernel_ms": mf_ms, "max_abs_dr_final": err_mf},
         "adjoint": adj,
         "ragged": rag,
         "rnn": rnn,
