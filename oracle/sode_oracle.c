@@ -30,7 +30,7 @@
 #include <string.h>
 
 enum { M_KURAMOTO = 0, M_OU = 1, M_GBM = 2, M_FHN = 3, M_RNN = 4 };
-enum { METHOD_EM = 0, METHOD_RK4 = 1 };
+enum { METHOD_EM = 0, METHOD_RK4 = 1, METHOD_MILSTEIN = 2 };
 enum { OBS_STATE = 0, OBS_KURAMOTO_R = 1 };
 
 /* ------------------------------------------------------------------------ */
@@ -233,6 +233,19 @@ void oracle_diffusion(int32_t model, int32_t n, int32_t m, int32_t d, double t,
     }
 }
 
+/* For the Milstein scheme: c_i = g_ii(X) * dg_ii/dX_i for each component.
+ * Every model here has diagonal noise whose i-th coefficient depends on X_i
+ * alone (or on nothing), the commutative case in which the order-one
+ * scheme needs no iterated integrals beyond (dW_i)^2.  Only geometric
+ * Brownian motion has a state-dependent coefficient, g_ii = s X_i.          */
+void oracle_diffusion_dgdx(int32_t model, int32_t n, int32_t m, int32_t d, double t,
+                           const double* X, const double* p, double* c)
+{
+    (void)m; (void)d; (void)t;
+    for (int32_t i = 0; i < n; ++i)
+        c[i] = model == M_GBM ? (p[1] * X[i]) * p[1] : 0.0;
+}
+
 /* Complex order parameter of Eq. (7), Sec. 2.3.1: r = |(1/N) sum_j e^{i theta_j}|. */
 double oracle_order_parameter(int32_t n, const double* theta)
 {
@@ -258,7 +271,11 @@ static void save_observable(int32_t observable, int32_t n, const double* X, doub
  * (Sec. 2.1.1; one call of the per-step integrator of Fig. 2 per step), or,
  * for method RK4, the classical four-stage Runge-Kutta scheme applied to the
  * ODE limit g = 0 (Sec. 1.1 last sentence; Sec. 1.5 lists Runge-Kutta among
- * the ODE methods).  The state is observed every `stride` steps, the host
+ * the ODE methods), or, for method MILSTEIN, the strong order-one Milstein
+ * scheme the paper names as its next stochastic method (Sec. 1.5, Sec. 4):
+ * the Euler-Maruyama increment plus (1/2) g_ii dg_ii/dX_i ((dW_i)^2 - dt)
+ * with dW_i = sqrt(dt) N_i, for diagonal noise (Kloeden & Platen, Numerical
+ * Solution of SDEs, Sec. 10.3).  The state is observed every `stride` steps, the host
  * loop of Sec. 2.1.4 (Eq. 4) with s = stride.
  *
  *   X0  [orbits][n]    p  [orbits][d] (p_per_orbit = 1) or [d] (= 0)
@@ -274,7 +291,8 @@ int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
                      int32_t method, int32_t observable, double* out)
 {
     if (!oracle_model_dims_ok(model, n, m, d) || orbits < 0 || nsteps < 0 || stride < 1 ||
-        nsteps % stride != 0 || (method != METHOD_EM && method != METHOD_RK4))
+        nsteps % stride != 0 ||
+        (method != METHOD_EM && method != METHOD_RK4 && method != METHOD_MILSTEIN))
         return -1;
     if (observable == OBS_KURAMOTO_R && model != M_KURAMOTO)
         return -1;
@@ -291,6 +309,7 @@ int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
     double* k3 = (double*)malloc(sizeof(double) * (size_t)n);
     double* k4 = (double*)malloc(sizeof(double) * (size_t)n);
     double* Y = (double*)malloc(sizeof(double) * (size_t)n);
+    double* c = (double*)malloc(sizeof(double) * (size_t)n);
     const double sqdt = sqrt(dt);
 
     for (int64_t o = 0; o < orbits; ++o) {
@@ -303,12 +322,20 @@ int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
 
         for (int64_t k = 0; k < nsteps; ++k) {
             double t = t0 + (double)k * dt;
-            if (method == METHOD_EM) {
+            if (method == METHOD_EM || method == METHOD_MILSTEIN) {
                 oracle_drift(model, n, m, d, t, X, po, f);
                 oracle_normals(sd, id, (uint32_t)(step_offset + (uint64_t)k), m, xi);
                 oracle_diffusion(model, n, m, d, t, X, po, xi, gx);
+                if (method == METHOD_MILSTEIN)
+                    oracle_diffusion_dgdx(model, n, m, d, t, X, po, c);
                 for (int32_t i = 0; i < n; ++i)
                     X[i] = X[i] + f[i] * dt + gx[i] * sqdt;
+                if (method == METHOD_MILSTEIN) {
+                    for (int32_t i = 0; i < n; ++i) {
+                        double dW = i < m ? sqdt * xi[i] : 0.0;
+                        X[i] = X[i] + 0.5 * c[i] * (dW * dW - dt);
+                    }
+                }
             } else {
                 oracle_drift(model, n, m, d, t, X, po, k1);
                 for (int32_t i = 0; i < n; ++i)
@@ -328,7 +355,7 @@ int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
         }
     }
     free(X); free(f); free(gx); free(xi);
-    free(k1); free(k2); free(k3); free(k4); free(Y);
+    free(k1); free(k2); free(k3); free(k4); free(Y); free(c);
     return 0;
 }
 

@@ -171,6 +171,50 @@ def test_gbm_strong_order_half(oracle_lib):
     assert 0.4 < slope < 0.62, (slope, errs)
 
 
+def test_gbm_milstein_strong_order_one(oracle_lib):
+    """Milstein for GBM against the same exact solution: strong error ~ dt.
+    A wrong coefficient of the (dW^2 - dt) correction (or its sign) leaves a
+    dt^{1/2} term and drops the slope back to one half."""
+    mu, s, x0, T, orbits = 1.0, 0.8, 1.0, 1.0, 2048
+    errs, dts = [], []
+    for L in range(4, 10):
+        nsteps = 2**L
+        dt = T / nsteps
+        X = oracle_lib.integrate("gbm", 1, 1, 2, np.full((orbits, 1), x0), [mu, s], 0.0, dt,
+                                 nsteps, nsteps, 500 + L, method="milstein")[:, -1, 0]
+        W = _brownian(oracle_lib, orbits, dt, nsteps, 500 + L)
+        exact = x0 * np.exp((mu - 0.5 * s * s) * T + s * W)
+        errs.append(np.mean(np.abs(X - exact)))
+        dts.append(dt)
+    slope = np.polyfit(np.log(dts), np.log(errs), 1)[0]
+    assert 0.88 < slope < 1.12, (slope, errs)
+
+
+def test_gbm_milstein_one_step_closed_form(oracle_lib):
+    """One Milstein step of GBM is X0 (1 + mu dt + s dW + s^2 (dW^2 - dt) / 2):
+    the second-order Taylor expansion of the exact solution's exponential in
+    dW, with dW^2 replaced by its mean where it multiplies mu."""
+    mu, s, x0, dt = 0.3, 0.9, 1.7, 0.04
+    X = oracle_lib.integrate("gbm", 1, 1, 2, np.full((64, 1), x0), [mu, s], 0.0, dt, 1, 1, 9,
+                             method="milstein")[:, -1, 0]
+    W = _brownian(oracle_lib, 64, dt, 1, 9)
+    want = x0 * (1 + mu * dt + s * W + 0.5 * s * s * (W * W - dt))
+    np.testing.assert_allclose(X, want, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("model,n,m,d,p", [("ou", 3, 3, 3, [0.7, 0.2, 0.3]),
+                                           ("kuramoto", 4, 4, 9, [1.5, 0.1, 0.2, -0.3, 0.4,
+                                                                  0.1, 0.2, 0.3, 0.05]),
+                                           ("fhn", 6, 3, 5, [0.7, 0.8, 0.08, 0.1, 0.05])])
+def test_milstein_equals_em_for_additive_noise(oracle_lib, model, n, m, d, p):
+    """With a state-independent diffusion the correction vanishes and the
+    Milstein iterates are the Euler-Maruyama iterates, bit for bit."""
+    X0 = np.random.default_rng(3).uniform(-1, 1, (5, n))
+    a = oracle_lib.integrate(model, n, m, d, X0, p, 0.0, 0.01, 40, 10, 5)
+    b = oracle_lib.integrate(model, n, m, d, X0, p, 0.0, 0.01, 40, 10, 5, method="milstein")
+    np.testing.assert_array_equal(a, b)
+
+
 def test_gbm_weak_mean(oracle_lib):
     """E X_K = X0 (1 + mu dt)^K exactly for the EM iterates of GBM."""
     mu, s, x0, dt, K, orbits = 0.5, 0.4, 2.0, 0.01, 100, 65536
