@@ -90,7 +90,13 @@ int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out)
  *   "method"       0 = Euler-Maruyama, Eq. (2) of Sec. 2.1.1 (default);
  *                  1 = classical RK4 on the ODE limit g = 0 (Sec. 1.1; the
  *                      Runge-Kutta ODE solver of Sec. 1.5): the diffusion is
- *                      ignored and no noise is drawn.
+ *                      ignored and no noise is drawn;
+ *                  2 = Milstein, the strong order-one scheme named as the
+ *                      next stochastic method (Sec. 1.5, Sec. 4), for
+ *                      diagonal noise: the EM increment plus
+ *                      (1/2) g_ii dg_ii/dX_i ((dW_i)^2 - dt).  Plain kernel
+ *                      only; for models whose diffusion does not depend on
+ *                      the state (all but "gbm") it equals EM exactly.
  *   "observable"   0 = state (q = n values per save);
  *                  1 = Kuramoto order parameter r of Eq. (7), Sec. 2.3.1
  *                      (q = 1; Kuramoto only).
@@ -208,7 +214,8 @@ int sode_adjoint(sode_t h, const void* p, int64_t orbits, double t0, double dt, 
  * length in one persistent launch (the paper runs one size per launch and
  * tunes the work-group size by hand, Sec. 2.2.2 and Table 4).
  *
- * Handle: model "fhn", precision 32 (else SODE_EUNSUPPORTED); every
+ * Handle: model "fhn", precision 32, method EM or Milstein (the same steps
+ * for this additive noise; else SODE_EUNSUPPORTED); every
  * instance has an even n with 2 <= n <= min(256, handle n), m = n/2, d = 5.
  *   inst   HOST array [count] of descriptors (read during the call only).
  *   X0, p, out  packed DEVICE arrays of x0_len, p_len, out_len floats; every

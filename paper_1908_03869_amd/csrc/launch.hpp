@@ -11,7 +11,7 @@
 namespace sode {
 
 enum ModelId : int { kKuramoto = 0, kOU = 1, kGBM = 2, kFHN = 3, kRNN = 4 };
-enum MethodId : int { kEM = 0, kRK4 = 1 };
+enum MethodId : int { kEM = 0, kRK4 = 1, kMilstein = 2 };
 enum ObservableId : int { kState = 0, kKuramotoR = 1 };
 
 // One integrate request, already checked for shape and range.

@@ -5,7 +5,11 @@
 //                            autonomous, so t is not an argument);
 //   diffuse(n, p, y, xi)     overwrites xi with sum_j g_ij xi_j (diagonal
 //                            noise: g_ij = 0 for i != j), without sqrt(dt);
-//   noises(n)                m, the number of Wiener processes.
+//   noises(n)                m, the number of Wiener processes;
+//   kStateNoise              whether g depends on the state; if it does,
+//   dgdx(n, p, y, c)         c_i = g_ii dg_ii/dX_i, the coefficient of the
+//                            Milstein correction (diagonal noise with g_ii a
+//                            function of X_i alone).
 // These are the two user functions of the paper's per-step integrator
 // (Sec. 2.1.3, Step 4, Fig. 3), fixed at compile time instead of being
 // assembled into a runtime-compiled source string.
@@ -28,6 +32,7 @@ __device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
 // parameter layout p = (K, omega_1..N, p_1..N) of that section's footnote:
 // f_i = omega_i + (K/N) sum_j sin(theta_j - theta_i), g_ij = p_i delta_ij.
 struct Kuramoto {
+    static constexpr bool kStateNoise = false;
     static constexpr int kId = 0;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>
@@ -56,6 +61,7 @@ struct Kuramoto {
 // which is exact in real arithmetic and costs O(N) instead of O(N^2)
 // sines (the mean-field form of the coupling, Sec. 2.3.1).
 struct KuramotoMeanField {
+    static constexpr bool kStateNoise = false;
     static constexpr int kId = 0;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>
@@ -81,6 +87,7 @@ struct KuramotoMeanField {
 
 // Ornstein-Uhlenbeck, dX_i = -a (X_i - mu) dt + s dW_i, p = (a, mu, s).
 struct OrnsteinUhlenbeck {
+    static constexpr bool kStateNoise = false;
     static constexpr int kId = 1;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>
@@ -99,6 +106,7 @@ struct OrnsteinUhlenbeck {
 
 // Geometric Brownian motion, dX_i = mu X_i dt + s X_i dW_i, p = (mu, s).
 struct GeometricBM {
+    static constexpr bool kStateNoise = true;
     static constexpr int kId = 2;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>
@@ -113,6 +121,12 @@ struct GeometricBM {
         for (int i = 0; i < n; ++i)
             xi[i] = p[1] * y[i] * xi[i];
     }
+    template <typename R>
+    __device__ static void dgdx(int n, const R* __restrict__ p, const R* y, R* c)
+    {
+        for (int i = 0; i < n; ++i)
+            c[i] = (p[1] * y[i]) * p[1];
+    }
 };
 
 // FitzHugh-Nagumo chain of N = n/2 units, state (v_1..v_N, w_1..w_N),
@@ -121,6 +135,7 @@ struct GeometricBM {
 //   dw_i = eps (v_i + a - b w_i) dt
 // with no-flux ends (v_0 = v_1, v_{N+1} = v_N); noise on v only, m = N.
 struct FhnChain {
+    static constexpr bool kStateNoise = false;
     static constexpr int kId = 3;
     __host__ __device__ static constexpr int noises(int n) { return n / 2; }
     template <typename R>
@@ -150,6 +165,7 @@ struct FhnChain {
 // Dense random recurrent network, dX = (-X + W tanh X + b) dt + sigma dW,
 // p = (W row-major n x n, b_1..n, sigma).
 struct DenseRnn {
+    static constexpr bool kStateNoise = false;
     static constexpr int kId = 4;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>

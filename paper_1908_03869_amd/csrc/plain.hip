@@ -50,9 +50,12 @@ __device__ __forceinline__ void save(const PlainArgs<R>& a, int n, const R* y, R
 }
 
 // NC > 0: the state dimension is the compile-time constant NC; NC == 0: the
-// runtime a.n (<= kPlainMaxN).  RK4 selects the classical Runge-Kutta
-// scheme on the drift alone (ODE limit) instead of Euler-Maruyama.
-template <class Model, typename R, int NC, bool RK4>
+// runtime a.n (<= kPlainMaxN).  METH: Euler-Maruyama (Eq. 2), the Milstein
+// scheme for diagonal state-dependent noise (the order-one method named as
+// the next step in Sec. 1.5 and Sec. 4: the EM increment plus
+// (1/2) g_ii dg_ii/dX_i ((dW_i)^2 - dt), dW_i = sqrt(dt) xi_i), or the
+// classical Runge-Kutta scheme on the drift alone (ODE limit).
+template <class Model, typename R, int NC, int METH>
 __global__ __launch_bounds__(64) void plain_kernel(const PlainArgs<R> a)
 {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(64) void plain_kernel(const PlainArgs<R> a)
     int64_t k = 0;
     for (int64_t s = 1; s < a.nsave; ++s) {
         for (int64_t kk = 0; kk < a.stride; ++kk, ++k) {
-            if constexpr (!RK4) {
+            if constexpr (METH == kEM) {
                 // Euler-Maruyama, Eq. (2): X += f dt + (G xi) sqrt(dt).
                 R f[CAP], xi[CAP];
                 Model::drift(n, p, y, f);
@@ -84,6 +87,21 @@ __global__ __launch_bounds__(64) void plain_kernel(const PlainArgs<R> a)
                 Model::diffuse(n, p, y, xi);
                 for (int i = 0; i < n; ++i)
                     y[i] = y[i] + f[i] * a.dt + xi[i] * a.sqdt;
+            } else if constexpr (METH == kMilstein) {
+                R f[CAP], xi[CAP], gxi[CAP], c[CAP];
+                Model::drift(n, p, y, f);
+                Model::dgdx(n, p, y, c);
+                normals<R>(st, (uint32_t)(a.step_offset + (uint64_t)k), m, xi);
+                for (int j = m; j < n; ++j)
+                    xi[j] = 0;
+                for (int i = 0; i < n; ++i)
+                    gxi[i] = xi[i];
+                Model::diffuse(n, p, y, gxi);
+                for (int i = 0; i < n; ++i) {
+                    const R dW = a.sqdt * xi[i];
+                    y[i] = y[i] + f[i] * a.dt + gxi[i] * a.sqdt;
+                    y[i] = y[i] + (R)0.5 * c[i] * (dW * dW - a.dt);
+                }
             } else {
                 // Classical RK4 on dX = f dt.
                 R kst[CAP], ksum[CAP], yt[CAP];
@@ -138,9 +156,12 @@ hipError_t launch_one(const Request& r)
     const dim3 block(64);
     const dim3 grid((unsigned)((r.orbits + 63) / 64));
     if (r.method == kRK4)
-        hipLaunchKernelGGL((plain_kernel<Model, R, NC, true>), grid, block, 0, r.stream, a);
-    else
-        hipLaunchKernelGGL((plain_kernel<Model, R, NC, false>), grid, block, 0, r.stream, a);
+        hipLaunchKernelGGL((plain_kernel<Model, R, NC, kRK4>), grid, block, 0, r.stream, a);
+    else if (r.method == kMilstein && Model::kStateNoise)
+        hipLaunchKernelGGL((plain_kernel<Model, R, NC, (Model::kStateNoise ? kMilstein : kEM)>),
+                           grid, block, 0, r.stream, a);
+    else  // EM; and Milstein with state-independent noise, where the correction is zero
+        hipLaunchKernelGGL((plain_kernel<Model, R, NC, kEM>), grid, block, 0, r.stream, a);
     return hipGetLastError();
 }
 

@@ -175,7 +175,7 @@ int sode_set_option(sode_t h, const char* key, int64_t value)
             return SODE_EINVAL;
         h->precision = (int)value;
     } else if (std::strcmp(key, "method") == 0) {
-        if (value != sode::kEM && value != sode::kRK4)
+        if (value != sode::kEM && value != sode::kRK4 && value != sode::kMilstein)
             return SODE_EINVAL;
         h->method = (int)value;
     } else if (std::strcmp(key, "observable") == 0) {

@@ -69,7 +69,7 @@ def test_options_round_trip_and_reject_unknown():
             assert abi.sode_set_option(h, key, val) == 0
             assert abi.sode_get_option(h, key) == (0, val)
         assert abi.sode_set_option(h, "precision", 16) == abi.SODE_EINVAL
-        assert abi.sode_set_option(h, "method", 2) == abi.SODE_EINVAL
+        assert abi.sode_set_option(h, "method", 3) == abi.SODE_EINVAL
         assert abi.sode_set_option(h, "kernel", 7) == abi.SODE_EINVAL
         assert abi.sode_set_option(h, "drift", 2) == abi.SODE_EINVAL
         assert abi.sode_set_option(h, "bogus", 1) == abi.SODE_EINVAL
@@ -241,6 +241,9 @@ def test_ragged_support_and_trivial_calls():
     assert _ragged(h, [_desc(n=18)]) == abi.SODE_EINVAL      # above the handle's n
     assert _ragged(h, []) == abi.SODE_OK                      # nothing to do
     assert _ragged(h, [_desc()], dt=0.0) == abi.SODE_EINVAL
+    abi.sode_set_option(h, "method", 1)                       # RK4: no ragged kernel
+    assert _ragged(h, [_desc()]) == abi.SODE_EUNSUPPORTED
+    abi.sode_set_option(h, "method", 0)
     abi.sode_set_option(h, "precision", 64)
     assert _ragged(h, [_desc()]) == abi.SODE_EUNSUPPORTED
     abi.sode_destroy(h)
