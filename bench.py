@@ -185,17 +185,19 @@ PAPER_M = (512, 5120, 25600, 40960, 81920, 163840)
 def paper_sweep(sode, torch, workloads, dev, reps: int) -> None:
     """The speed protocol of Sec. 2.2.1 (Tables S1-S3): Kuramoto N in
     {5, 10, 15}, M orbits from 512 to 163,840, K = 1, 8000 Euler-Maruyama
-    steps of 0.05 s, in binary64 and binary32, with the pairwise and the
-    mean-field drift.  One JSON line per case: the kernel time with inputs
+    steps of 0.05 s, in binary64 and binary32 on the one-orbit-per-lane
+    kernel and in binary32 on the 16-lane kernel (padded rows), with the
+    pairwise and the mean-field drift.  One JSON line per case: the kernel time with inputs
     resident in HBM and the host-to-host time (upload of X0 and p, the
     integration, download of the saved states), each the median of `reps`
     runs after one warm-up."""
-    for prec in (64, 32):
+    cases = [(64, "plain"), (32, "plain"), (32, "coupled")]
+    for prec, kernel in cases:
         dtype = torch.float64 if prec == 64 else torch.float32
         for N in PAPER_N:
             for drift in ("pairwise", "meanfield"):
                 it = sode.Integrator("kuramoto", N, N, 2 * N + 1, precision=prec,
-                                     kernel="plain", drift=drift)
+                                     kernel=kernel, drift=drift)
                 for M in PAPER_M:
                     w = workloads.kuramoto_paper(N, M)
                     X0h = torch.tensor(w["X0"], dtype=dtype).pin_memory()
@@ -227,8 +229,8 @@ def paper_sweep(sode, torch, workloads, dev, reps: int) -> None:
                         host.append((time.perf_counter() - h0) * 1e3)
                     k_ms, h_ms = float(np.median(kern)), float(np.median(host))
                     print(json.dumps({
-                        "sweep": "paper_kuramoto", "precision": prec, "N": N, "M": M,
-                        "drift": drift, "nsteps": w["nsteps"], "stride": w["stride"],
+                        "sweep": "paper_kuramoto", "precision": prec, "kernel": kernel, "N": N,
+                        "M": M, "drift": drift, "nsteps": w["nsteps"], "stride": w["stride"],
                         "kernel_ms": k_ms, "host_ms": h_ms,
                         "orbit_steps_per_s": M * w["nsteps"] / (k_ms * 1e-3)}), flush=True)
                 it.close()

@@ -102,10 +102,21 @@ int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out)
  *                      (q = 1; Kuramoto only).
  *   "kernel"       0 = auto; 1 = plain (one orbit per lane, any model,
  *                  either precision); 2 = coupled (Kuramoto, precision 32,
- *                  method EM, n a multiple of 16 up to 128: 16 lanes per
- *                  orbit exchange phases through DPP row rotations).
+ *                  method EM, n <= 128: 16 lanes per orbit exchange phases
+ *                  through DPP row rotations; an n that is not a multiple
+ *                  of 16 runs padded with oscillators frozen at phase 0
+ *                  whose coupling is cancelled); 3 = matrix (see "gemm").
+ *                  Auto takes coupled for binary32 Kuramoto EM with
+ *                  8 <= n <= 128 (n < 8: only up to 65,536 orbits),
+ *                  matrix for a supported dense network, else plain.
  *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
  *                  used by every orbit.
+ *   "gemm"         matrix kernel (model "rnn", precision 32, method EM,
+ *                  shared_params 1, n in {64, 128, 256}): the drift product
+ *                  W tanh(X) on the matrix cores as 0 = one bfloat16
+ *                  product, 1 = bfloat16 split into hi + lo with the three
+ *                  products hi.hi + hi.lo + lo.hi (default), 2 = binary32
+ *                  products; accumulation is binary32 in every case.
  *   "drift"        Kuramoto coupling sum: 0 = pairwise sines as in Fig. 5
  *                  (default); 1 = the exactly equivalent mean-field form
  *                  cos(theta_i) sum_j sin(theta_j) - sin(theta_i) sum_j

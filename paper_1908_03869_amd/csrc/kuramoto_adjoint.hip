@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjointArgs a)
             const float A = row_sum(la), B = row_sum(lb);
 #pragma unroll
             for (int i = 0; i < P; ++i)
-                lam[i] += c.kc * (cs[i] * A + sn[i] * B - lam[i] * (cs[i] * C + sn[i] * S));
+                lam[i] += c.kc[0] * (cs[i] * A + sn[i] * B - lam[i] * (cs[i] * C + sn[i] * S));
             if (in_window(k, a.win_lo, a.win_hi))
                 add_window_seed<P>(lam, cs, sn, C, S, a.inv_window);
         }
@@ -344,5 +344,7 @@ hipError_t launch_kuramoto_adjoint_f32(const AdjointRequest& r)
     default: return hipErrorInvalidValue;
     }
 }
+
+bool adjoint_supports(int n) { return n == 16 || n == 32 || n == 64 || n == 128; }
 
 }  // namespace sode

@@ -27,6 +27,14 @@
 // orbit-step this is N(N-1)/2 + N^2/32 sines instead of N^2.
 //
 // Noise: lane l needs normals P*l .. P*l+P-1 (lane_normals, noise.hpp).
+//
+// Padding (PAD): a system of N oscillators with N not a multiple of 16 runs
+// as 16P = 16 ceil(N/16) oscillators, the Q = 16P - N extra ones held at
+// phase 0 with zero frequency, coupling and noise coefficients, so they never
+// move.  Each pad adds sin(0 - theta_i) to a real oscillator's sum; adding
+// Q sin(theta_i) back once per step removes it (exact in real arithmetic,
+// one sine per oscillator instead of a mask per pair).  Mean-field sums and
+// the order parameter weight pads by 0 and divide by N.
 #pragma once
 
 #include "noise.hpp"
@@ -141,27 +149,39 @@ __device__ __forceinline__ float row_sum(float v)
 }
 
 // Per-lane constants of the Euler-Maruyama map in radians: omega_i dt,
-// p_i sqrt(dt) and K dt / N.
-template <int P>
+// p_i sqrt(dt) and K dt / N; with padding, K dt / N and a weight per
+// oscillator (0 for pads) and the pad count Q.
+template <int P, bool PAD = false>
 struct LaneCoefficients {
     float drift0[P];
     float noise_scale[P];
-    float kc;
+    float kc[PAD ? P : 1];
+    float weight[PAD ? P : 1];
+    float pads;
 };
 
-template <int P>
-__device__ __forceinline__ LaneCoefficients<P> lane_coefficients(const float* __restrict__ p, int l,
-                                                                 float dt, float sqdt, float dt_over_n)
+// p = (K, omega_1..N, p_1..N) of the N-oscillator system (N = n_real).
+template <int P, bool PAD = false>
+__device__ __forceinline__ LaneCoefficients<P, PAD> lane_coefficients(const float* __restrict__ p, int l,
+                                                                      float dt, float sqdt, float dt_over_n,
+                                                                      int n_real = 16 * P)
 {
-    constexpr int N = 16 * P;
-    LaneCoefficients<P> c;
+    LaneCoefficients<P, PAD> c;
+    const float kc = p[0] * dt_over_n;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const int osc = P * l + i;
-        c.drift0[i] = p[1 + osc] * dt;
-        c.noise_scale[i] = p[1 + N + osc] * sqdt;
+        const bool real = !PAD || osc < n_real;
+        c.drift0[i] = real ? p[1 + osc] * dt : 0.0f;
+        c.noise_scale[i] = real ? p[1 + n_real + osc] * sqdt : 0.0f;
+        if constexpr (PAD) {
+            c.kc[i] = real ? kc : 0.0f;
+            c.weight[i] = real ? 1.0f : 0.0f;
+        }
     }
-    c.kc = p[0] * dt_over_n;
+    if constexpr (!PAD)
+        c.kc[0] = kc;
+    c.pads = (float)(16 * P - n_real);
     return c;
 }
 
@@ -172,16 +192,22 @@ __device__ __forceinline__ float load_phase(float x) { return __builtin_fabsf(x)
 // Coupling sums through the angle-difference identity:
 // sum_j sin(theta_j - theta_i) = cos(theta_i) S - sin(theta_i) C with the row
 // sums C = sum cos, S = sum sin -- O(N) per orbit instead of N(N-1)/2 sines.
-template <int P>
-__device__ __forceinline__ void mean_field_sums(const float (&phi)[P], float (&acc)[P])
+template <int P, bool PAD>
+__device__ __forceinline__ void mean_field_sums(const float (&phi)[P], float (&acc)[P],
+                                                const LaneCoefficients<P, PAD>& co)
 {
     float cs[P], sn[P], c = 0.0f, s = 0.0f;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         cs[i] = cos_rev(phi[i]);
         sn[i] = sin_rev(phi[i]);
-        c += cs[i];
-        s += sn[i];
+        if constexpr (PAD) {
+            c += cs[i] * co.weight[i];
+            s += sn[i] * co.weight[i];
+        } else {
+            c += cs[i];
+            s += sn[i];
+        }
     }
     const float C = row_sum(c), S = row_sum(s);
 #pragma unroll
@@ -194,23 +220,30 @@ __device__ __forceinline__ void mean_field_sums(const float (&phi)[P], float (&a
 // COMP: th is the leading part of hi + lo and tl the trailing part; the
 // increment and the old trailing part are added with an error-free two-sum,
 // and a wrap moves the tail of 2 pi into tl.  MF: coupling through the
-// mean-field identity instead of pairwise sines.
-template <int P, bool COMP, bool MF = false>
-__device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const LaneCoefficients<P>& c,
+// mean-field identity instead of pairwise sines.  PAD: see the top of the file.
+template <int P, bool COMP, bool MF = false, bool PAD = false>
+__device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const LaneCoefficients<P, PAD>& c,
                                         const Stream& st, uint32_t k, int l)
 {
     float phi[P], acc[P], xi[P];
 #pragma unroll
     for (int i = 0; i < P; ++i)
         phi[i] = th[i] * kInvTwoPi;
-    if constexpr (MF)
-        mean_field_sums<P>(phi, acc);
-    else
+    if constexpr (MF) {
+        mean_field_sums<P, PAD>(phi, acc, c);
+    } else {
         coupling_sums<P>(phi, acc);
+        if constexpr (PAD) {
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                acc[i] = __builtin_fmaf(c.pads, sin_rev(phi[i]), acc[i]);
+        }
+    }
     lane_normals<P>(st, k, l, xi);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-        const float inc = __builtin_fmaf(c.noise_scale[i], xi[i], __builtin_fmaf(c.kc, acc[i], c.drift0[i]));
+        const float kc = PAD ? c.kc[i] : c.kc[0];
+        const float inc = __builtin_fmaf(c.noise_scale[i], xi[i], __builtin_fmaf(kc, acc[i], c.drift0[i]));
         if constexpr (COMP) {
             const float y = inc + tl[i];
             const float s = th[i] + y;
@@ -249,6 +282,21 @@ __device__ __forceinline__ float order_parameter(const float (&th)[P])
     float cs[P], sn[P], C, S;
     phase_sums<P>(th, cs, sn, C, S);
     return __builtin_sqrtf(C * C + S * S) * (1.0f / (float)(16 * P));
+}
+
+// The same over the N real oscillators of a padded row (weights 0 for pads).
+template <int P>
+__device__ __forceinline__ float order_parameter_padded(const float (&th)[P], const float (&weight)[P], float inv_n)
+{
+    float c = 0.0f, s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const float rev = th[q] * kInvTwoPi;
+        c += cos_rev(rev) * weight[q];
+        s += sin_rev(rev) * weight[q];
+    }
+    const float C = row_sum(c), S = row_sum(s);
+    return __builtin_sqrtf(C * C + S * S) * inv_n;
 }
 
 }  // namespace kuramoto

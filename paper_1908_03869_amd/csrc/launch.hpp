@@ -43,8 +43,11 @@ constexpr int kPlainMaxN = 128;
 hipError_t launch_plain_f64(const Request& r);
 hipError_t launch_plain_f32(const Request& r);
 
-// Kuramoto, binary32, Euler-Maruyama: 16 lanes per orbit.
+// Kuramoto, binary32, Euler-Maruyama: 16 lanes per orbit, any n <= 128
+// (sizes that are not multiples of 16 run padded).  The checkpointed forward
+// pass and the adjoint take n in {16, 32, 64, 128}.
 bool coupled_supports(int n);
+bool adjoint_supports(int n);
 hipError_t launch_kuramoto_coupled_f32(const Request& r);
 
 // Checkpointed forward pass and adjoint of the window-averaged order

@@ -128,9 +128,11 @@ __device__ __forceinline__ void normals(const Stream& st, uint32_t k, int m, R* 
 }
 
 // Normals P*l .. P*l+P-1 of one orbit at global step k, for a lane l that
-// owns P consecutive state components (P = 1, 2 or a multiple of 4): the
-// Philox blocks floor(P*l/4) .. floor((P*l+P-1)/4), of which lanes with
-// P < 4 compute one block and keep their share of it.
+// owns P consecutive state components (P = 1..8): the Philox blocks
+// floor(P*l/4) .. floor((P*l+P-1)/4).  Lanes with P < 4 and P a power of two
+// compute one block and keep their share of it; for P = 3, 5, 6, 7 the
+// lane's range starts at word (P*l) mod 4 of its first block and touches at
+// most ceil((P+3)/4) blocks, all of which the lane evaluates.
 template <int P>
 __device__ __forceinline__ void lane_normals(const Stream& st, uint32_t k, int l, float (&xi)[P])
 {
@@ -145,13 +147,27 @@ __device__ __forceinline__ void lane_normals(const Stream& st, uint32_t k, int l
         const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)(l >> 1), 0u, st.key_lo, st.key_hi);
         const bool upper = (l & 1) != 0;
         box_muller_f32(upper ? w.w2 : w.w0, upper ? w.w3 : w.w1, xi[0], xi[1]);
-    } else {
-        static_assert(P == 1, "oscillators per lane");
+    } else if constexpr (P == 1) {
         const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)(l >> 2), 0u, st.key_lo, st.key_hi);
         const bool upper = (l & 2) != 0;
         float zc, zs;
         box_muller_f32(upper ? w.w2 : w.w0, upper ? w.w3 : w.w1, zc, zs);
         xi[0] = (l & 1) ? zs : zc;
+    } else {
+        static_assert(P > 2 && P < 8, "oscillators per lane");
+        constexpr int NB = (P + 6) / 4;
+        const int j0 = P * l;
+        const int off = j0 & 3;
+        float z[4 * NB];
+#pragma unroll
+        for (int g = 0; g < NB; ++g) {
+            const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)((j0 >> 2) + g), 0u, st.key_lo, st.key_hi);
+            box_muller_f32(w.w0, w.w1, z[4 * g + 0], z[4 * g + 1]);
+            box_muller_f32(w.w2, w.w3, z[4 * g + 2], z[4 * g + 3]);
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            xi[i] = off == 0 ? z[i] : off == 1 ? z[i + 1] : off == 2 ? z[i + 2] : z[i + 3];
     }
 }
 

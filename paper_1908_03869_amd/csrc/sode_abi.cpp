@@ -85,7 +85,7 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
     if (step_offset > (1ull << 32) || (uint64_t)nsteps > (1ull << 32) - step_offset)
         return SODE_EINVAL;
     if (h->model != sode::kKuramoto || h->precision != 32 || h->method != sode::kEM ||
-        !sode::coupled_supports(h->n))
+        !sode::adjoint_supports(h->n))
         return SODE_EUNSUPPORTED;
     // Checkpoints [orbits][nsteps/every + 1][n] must fit 64-bit byte offsets.
     if (orbits > 0 && nsteps / every + 1 > (INT64_MAX / 16) / orbits / h->n)
@@ -94,7 +94,11 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
 }
 
 // Which kernel a request goes to; SODE_EUNSUPPORTED if none can run it.
-int choose_kernel(const sode_ctx* h, int* kernel)
+// Auto: the 16-lane Kuramoto kernel wherever it applies, except for fewer
+// than 8 oscillators over many orbits, where a padded row wastes most of its
+// lanes and one orbit per lane fills the chip anyway (measured crossover:
+// between 40,960 and 81,920 orbits at n = 5).
+int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 {
     const bool coupled_ok = h->model == sode::kKuramoto && h->precision == 32 &&
                             h->method == sode::kEM && sode::coupled_supports(h->n);
@@ -113,7 +117,7 @@ int choose_kernel(const sode_ctx* h, int* kernel)
         if (!plain_ok)
             return SODE_EUNSUPPORTED;
         *kernel = 1;
-    } else if (coupled_ok) {
+    } else if (coupled_ok && (h->n >= 8 || orbits <= 65536)) {
         *kernel = 2;
     } else if (matrix_ok) {
         *kernel = 3;
@@ -284,7 +288,7 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
     if (orbits > 0 && nsave > (INT64_MAX / 16) / orbits / q)
         return SODE_EINVAL;
     int kernel = 0;
-    const int choice = choose_kernel(h, &kernel);
+    const int choice = choose_kernel(h, orbits, &kernel);
     if (choice != SODE_OK)
         return choice;
     if (orbits == 0)

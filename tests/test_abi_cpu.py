@@ -116,8 +116,8 @@ def test_integrate_null_handle_and_zero_orbits():
 
 
 def test_unsupported_kernel_requests():
-    st, h = abi.sode_create("kuramoto", 12, 12, 25)
-    abi.sode_set_option(h, "kernel", 2)  # coupled needs n in {16, 32, 64, 128}
+    st, h = abi.sode_create("kuramoto", 130, 130, 261)
+    abi.sode_set_option(h, "kernel", 2)  # coupled needs n <= 128
     assert _call(h) == abi.SODE_EUNSUPPORTED
     abi.sode_destroy(h)
     st, h = abi.sode_create("kuramoto", 64, 64, 129)
