@@ -13,7 +13,8 @@ Printed JSON line (rank 0): the driver's contract fields plus
   error         max |dr| against the oracle on the sampled orbits,
   meanfield     the same ensemble with the O(n) mean-field drift form,
 and the adjoint, ragged-batch and dense-network legs.  --paper-sweep REPS
-prints the Sec. 2.2.1 speed protocol instead (one line per case).
+prints the Sec. 2.2.1 speed protocol instead (one line per case), and
+--accuracy-study R the Sec. 2.3.1 accuracy study with R realisations.
 """
 from __future__ import annotations
 
@@ -38,6 +39,11 @@ VALU_LANE_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # transcendentals (sin, cos, log2, sqrt) are quarter rate, 32-bit integer
 # multiplies (high or low half) and binary64 FMAs half rate.
 SLOTS = {"valu": 1.0, "trans": 4.0, "imul": 2.0}
+# HBM bytes per launch of the n = 64 grid kernel as measured with rocprofv3
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a 1 GiB copy shows), for
+# the kernel as built from the current sources; the algorithmic figure is
+# 103.3 MB (X0 and p read once, r written once).
+COUPLED_N64_HBM_BYTES = 50.97e6 + 53.00e6
 
 
 def algorithmic_slots_per_orbit_step(n: int, compensated: bool = True) -> dict:
@@ -236,6 +242,56 @@ def paper_sweep(sode, torch, workloads, dev, reps: int) -> None:
                 it.close()
 
 
+def accuracy_study(sode, torch, workloads, dev, realisations: int, oracle_threads: int) -> None:
+    """The accuracy and stability study of Sec. 2.3.1: N = 100 Kuramoto,
+    omega ~ U(0.2, 0.4), noise strengths ~ U(0.01, 0.03), K in {0.02, 0.2},
+    400 s at dt = 2^(l-5)/5 for l = 1..5, r(t) every 20 s.  Per (K, l), one
+    binary32 launch of the 16-lane kernel (padded rows) over all
+    realisations, then <r(t)> and sigma(r(t)) over the realisations from
+    sode_ensemble_stats; the FP64 oracle integrates the same realisations
+    (same Philox streams) on the host and its statistics and the pathwise
+    max |dr| are printed beside them.  One JSON line per (K, l)."""
+    import oracle
+
+    for K in (0.02, 0.2):
+        for level in (1, 2, 3, 4, 5):
+            w = workloads.kuramoto_e4(K, realisations=realisations, level=level)
+            n = w["n"]
+            it = sode.Integrator("kuramoto", n, n, w["d"], precision=32, kernel="coupled",
+                                 observable="kuramoto_r")
+            X0 = torch.tensor(w["X0"], dtype=torch.float32, device=dev)
+            p = torch.tensor(w["p"], dtype=torch.float32, device=dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            stream = torch.cuda.current_stream()
+            e0.record(stream)
+            r = it.integrate(X0, p, 0.0, w["dt"], w["nsteps"], w["stride"], w["seed"])
+            e1.record(stream)
+            mean, std = it.ensemble_stats(r[:, :, 0].contiguous())
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            r_gpu = r[:, :, 0].double().cpu().numpy()
+            it.close()
+            c0 = time.perf_counter()
+            X32 = w["X0"].astype(np.float32).astype(np.float64)
+            p32 = w["p"].astype(np.float32).astype(np.float64)
+            ref = oracle.integrate_parallel("kuramoto", n, n, w["d"], X32, p32, 0.0, w["dt"],
+                                            w["nsteps"], w["stride"], w["seed"],
+                                            threads=oracle_threads,
+                                            observable="kuramoto_r")[:, :, 0]
+            cpu_s = time.perf_counter() - c0
+            t = (np.arange(ref.shape[1]) * w["stride"] * w["dt"]).tolist()
+            print(json.dumps({
+                "study": "kuramoto_e4", "K": K, "level": level, "dt": w["dt"],
+                "nsteps": w["nsteps"], "realisations": realisations, "t": t,
+                "mean_r": mean.cpu().numpy().tolist(), "std_r": std.cpu().numpy().tolist(),
+                "oracle_mean_r": ref.mean(axis=0).tolist(),
+                "oracle_std_r": ref.std(axis=0, ddof=1).tolist(),
+                "max_abs_dr": float(np.max(np.abs(r_gpu - ref))),
+                "gpu_ms": ms, "oracle_s": cpu_s, "oracle_threads": oracle_threads}),
+                flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +302,10 @@ def parse():
     ap.add_argument("--cpu-orbits", type=int, default=4,
                     help="orbits of the oracle sample (full 2x10^4 steps each)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--accuracy-study", type=int, default=0, metavar="REALISATIONS",
+                    help="instead of the benchmark line, run the Sec. 2.3.1 accuracy study "
+                         "with this many realisations per (K, dt), oracle alongside")
+    ap.add_argument("--oracle-threads", type=int, default=16)
     ap.add_argument("--paper-sweep", type=int, default=0, metavar="REPS",
                     help="instead of the benchmark line, time the Sec. 2.2.1 speed protocol "
                          "(N x M x precision x drift form), REPS runs per case")
@@ -270,6 +330,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.paper_sweep:
         paper_sweep(sode, torch, workloads, dev, args.paper_sweep)
+        return
+    if args.accuracy_study:
+        accuracy_study(sode, torch, workloads, dev, args.accuracy_study, args.oracle_threads)
         return
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
@@ -386,7 +449,8 @@ def main():
                      "peak": VALU_LANE_SLOTS_PER_S / 1e12,
                      "unit": "T VALU lane-slots/s (1 slot = one binary32 FMA)",
                      "frac": achieved / VALU_LANE_SLOTS_PER_S,
-                     "traffic": None, "kernel_ms": kernel_ms,
+                     "traffic": COUPLED_N64_HBM_BYTES, "traffic_unit": "HBM bytes per launch",
+                     "kernel_ms": kernel_ms,
                      "slots_per_orbit_step": work["slots"]},
         "cpu_baseline": cpu,
         "plain_fp64": {"value": plain_rate, "unit": "orbit*steps/s", "nsteps": bsteps,

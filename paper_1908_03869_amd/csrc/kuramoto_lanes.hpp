@@ -56,13 +56,15 @@ constexpr float kTwoPiTail = -1.74845553146951715461e-07f;
 constexpr float kPiF = 3.14159274101257324219f;  // binary32 pi, just above pi
 
 // Value of `v` held by another lane of the same 16-lane row, selected by a
-// DPP row rotation (control 0x120 + r, r = 1..15).
+// DPP row rotation (control 0x120 + r, r = 1..15).  A rotation has no
+// invalid source lane, so bound_ctrl is set only to tell the compiler that
+// the old destination value is never used (no register is cleared for it).
 template <int R>
 __device__ __forceinline__ float row_rotate(float v)
 {
     static_assert(R >= 1 && R <= 15, "row rotation amount");
     return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x120 + R, 0xF, 0xF, false));
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x120 + R, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }

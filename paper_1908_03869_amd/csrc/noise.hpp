@@ -31,14 +31,13 @@ __device__ __forceinline__ Block4 philox_4x32_10(uint32_t c0, uint32_t c1, uint3
     constexpr uint32_t kWeylHi = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(kMulEven0, c0);
-        const uint32_t lo0 = kMulEven0 * c0;
-        const uint32_t hi2 = __umulhi(kMulEven2, c2);
-        const uint32_t lo2 = kMulEven2 * c2;
-        c0 = hi2 ^ c1 ^ key_lo;
-        c1 = lo2;
-        c2 = hi0 ^ c3 ^ key_hi;
-        c3 = lo0;
+        // One 32x32 -> 64-bit product per even word (a single v_mad_u64_u32).
+        const uint64_t p0 = (uint64_t)kMulEven0 * c0;
+        const uint64_t p2 = (uint64_t)kMulEven2 * c2;
+        c0 = (uint32_t)(p2 >> 32) ^ c1 ^ key_lo;
+        c1 = (uint32_t)p2;
+        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ key_hi;
+        c3 = (uint32_t)p0;
         key_lo += kWeylLo;
         key_hi += kWeylHi;
     }

@@ -42,3 +42,28 @@ def test_reproducible(gpu):
     b = _stats(x, 64)
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_accuracy_study_statistics(gpu):
+    """The Sec. 2.3.1 statistics end to end: r(t) of 16 realisations of the
+    N = 100 system (K = 0.02, dt = 0.2, 400 s) from the padded 16-lane
+    kernel, reduced on the GPU, against numpy's mean and standard deviation
+    of the FP64 oracle's r(t) on the same realisations."""
+    import torch
+    import paper_1908_03869_amd as sode
+    import workloads
+    from gpu_util import run_oracle
+    w = dict(workloads.kuramoto_e4(0.02, realisations=16, level=5), observable="kuramoto_r")
+    log("accuracy-study statistics K=0.02 level 5")
+    it = sode.Integrator("kuramoto", 100, 100, 201, precision=32, kernel="coupled",
+                         observable="kuramoto_r")
+    X0 = torch.tensor(w["X0"], dtype=torch.float32, device="cuda")
+    p = torch.tensor(w["p"], dtype=torch.float32, device="cuda")
+    r = it.integrate(X0, p, 0.0, w["dt"], w["nsteps"], w["stride"], w["seed"])
+    mean, std = it.ensemble_stats(r)
+    it.sync()
+    mean, std = mean.cpu().numpy()[:, 0], std.cpu().numpy()[:, 0]
+    it.close()
+    ref = run_oracle(w, precision=32)[:, :, 0]
+    np.testing.assert_allclose(mean, ref.mean(axis=0), rtol=0, atol=1e-4)
+    np.testing.assert_allclose(std, ref.std(axis=0, ddof=1), rtol=0, atol=1e-4)
