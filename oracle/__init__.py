@@ -22,7 +22,7 @@ SRC = os.path.join(HERE, "sode_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 MODELS = {"kuramoto": 0, "ou": 1, "gbm": 2, "fhn": 3, "rnn": 4}
-METHODS = {"em": 0, "rk4": 1, "milstein": 2}
+METHODS = {"em": 0, "rk4": 1, "milstein": 2, "implicit_euler": 3, "implicit_midpoint": 4}
 OBSERVABLES = {"state": 0, "kuramoto_r": 1}
 
 _lib = None

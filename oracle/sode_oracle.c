@@ -30,7 +30,13 @@
 #include <string.h>
 
 enum { M_KURAMOTO = 0, M_OU = 1, M_GBM = 2, M_FHN = 3, M_RNN = 4 };
-enum { METHOD_EM = 0, METHOD_RK4 = 1, METHOD_MILSTEIN = 2 };
+enum {
+    METHOD_EM = 0,
+    METHOD_RK4 = 1,
+    METHOD_MILSTEIN = 2,
+    METHOD_IMPLICIT_EULER = 3,
+    METHOD_IMPLICIT_MIDPOINT = 4
+};
 enum { OBS_STATE = 0, OBS_KURAMOTO_R = 1 };
 
 /* ------------------------------------------------------------------------ */
@@ -267,6 +273,140 @@ static void save_observable(int32_t observable, int32_t n, const double* X, doub
 }
 
 /* ------------------------------------------------------------------------ */
+/* A system as the integrator sees it: sizes and the three model functions
+ * (drift f, diffusion G xi, and g_ii dg_ii/dX_i for Milstein).  Built-in
+ * models go through the switch functions above; a runtime-defined model
+ * supplies its own (oracle_integrate_custom).                               */
+typedef void (*drift_cb)(double t, const double* X, const double* p, double* f);
+typedef void (*diffusion_cb)(double t, const double* X, const double* p, const double* xi,
+                             double* gx);
+
+struct oracle_system {
+    int32_t model; /* built-in model id, or -1 for callbacks */
+    int32_t n, m, d;
+    drift_cb drift;
+    diffusion_cb diffusion;
+};
+
+static void sys_drift(const struct oracle_system* s, double t, const double* X, const double* p,
+                      double* f)
+{
+    if (s->model >= 0)
+        oracle_drift(s->model, s->n, s->m, s->d, t, X, p, f);
+    else
+        s->drift(t, X, p, f);
+}
+
+static void sys_diffusion(const struct oracle_system* s, double t, const double* X,
+                          const double* p, const double* xi, double* gx)
+{
+    if (s->model >= 0)
+        oracle_diffusion(s->model, s->n, s->m, s->d, t, X, p, xi, gx);
+    else if (s->diffusion)
+        s->diffusion(t, X, p, xi, gx);
+    else
+        for (int32_t i = 0; i < s->n; ++i)
+            gx[i] = 0.0;
+}
+
+static void sys_dgdx(const struct oracle_system* s, double t, const double* X, const double* p,
+                     double* c)
+{
+    if (s->model >= 0)
+        oracle_diffusion_dgdx(s->model, s->n, s->m, s->d, t, X, p, c);
+    else
+        for (int32_t i = 0; i < s->n; ++i)
+            c[i] = 0.0;
+}
+
+/* Solve A x = b in place (A n x n row-major, overwritten; b becomes x) by
+ * Gaussian elimination with partial pivoting.                                */
+static void solve_dense(int32_t n, double* A, double* b)
+{
+    for (int32_t col = 0; col < n; ++col) {
+        int32_t piv = col;
+        for (int32_t r = col + 1; r < n; ++r)
+            if (fabs(A[r * n + col]) > fabs(A[piv * n + col]))
+                piv = r;
+        if (piv != col) {
+            for (int32_t c = 0; c < n; ++c) {
+                double tmp = A[col * n + c];
+                A[col * n + c] = A[piv * n + c];
+                A[piv * n + c] = tmp;
+            }
+            double tb = b[col];
+            b[col] = b[piv];
+            b[piv] = tb;
+        }
+        for (int32_t r = col + 1; r < n; ++r) {
+            double l = A[r * n + col] / A[col * n + col];
+            for (int32_t c = col; c < n; ++c)
+                A[r * n + c] = A[r * n + c] - l * A[col * n + c];
+            b[r] = b[r] - l * b[col];
+        }
+    }
+    for (int32_t r = n - 1; r >= 0; --r) {
+        double acc = b[r];
+        for (int32_t c = r + 1; c < n; ++c)
+            acc = acc - A[r * n + c] * b[c];
+        b[r] = acc / A[r * n + r];
+    }
+}
+
+/* One step of an implicit one-stage Runge-Kutta method for the ODE limit
+ * g = 0 (the implicit solvers of Sec. 1.5; the implicit midpoint rule is the
+ * one the authors' earlier stiff-model work used, Sec. 3):
+ *     Y = X + dt f(t + c dt, X + c (Y - X)),
+ * c = 1 for implicit Euler, c = 1/2 for the implicit midpoint rule.  Y is
+ * found by Newton's method on G(Y) = Y - X - dt f(t + c dt, Z),
+ * Z = X + c (Y - X), starting from the explicit Euler predictor; the
+ * Jacobian of f at Z is formed by forward differences with step
+ * sqrt(eps) max(1, |Z_j|), and each Newton system I - c dt J is solved by
+ * Gaussian elimination with partial pivoting.  Iteration stops when the
+ * largest correction is at most 64 eps (1 + max |Y|) (eps = 2^-52), or after
+ * 50 iterations.  X is overwritten with Y.                                   */
+static void implicit_step(const struct oracle_system* s, double t, double dt, double c,
+                          const double* p, double* X, double* Y, double* Z, double* fz,
+                          double* fh, double* A, double* delta)
+{
+    const int32_t n = s->n;
+    const double eps = 0x1p-52;
+    sys_drift(s, t, X, p, fz);
+    for (int32_t i = 0; i < n; ++i)
+        Y[i] = X[i] + dt * fz[i];
+    const double ts = t + c * dt;
+    for (int32_t it = 0; it < 50; ++it) {
+        for (int32_t i = 0; i < n; ++i)
+            Z[i] = X[i] + c * (Y[i] - X[i]);
+        sys_drift(s, ts, Z, p, fz);
+        for (int32_t j = 0; j < n; ++j) {
+            double zj = Z[j];
+            double h = sqrt(eps) * (fabs(zj) > 1.0 ? fabs(zj) : 1.0);
+            Z[j] = zj + h;
+            h = Z[j] - zj;
+            sys_drift(s, ts, Z, p, fh);
+            Z[j] = zj;
+            for (int32_t i = 0; i < n; ++i)
+                A[i * n + j] = (i == j ? 1.0 : 0.0) - c * dt * ((fh[i] - fz[i]) / h);
+        }
+        for (int32_t i = 0; i < n; ++i)
+            delta[i] = -(Y[i] - X[i] - dt * fz[i]);
+        solve_dense(n, A, delta);
+        double dmax = 0.0, ymax = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            Y[i] = Y[i] + delta[i];
+            if (fabs(delta[i]) > dmax)
+                dmax = fabs(delta[i]);
+            if (fabs(Y[i]) > ymax)
+                ymax = fabs(Y[i]);
+        }
+        if (dmax <= 64.0 * eps * (1.0 + ymax))
+            break;
+    }
+    memcpy(X, Y, sizeof(double) * (size_t)n);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Integrate every orbit.  Per orbit, the Euler-Maruyama recursion of Eq. (2)
  * (Sec. 2.1.1; one call of the per-step integrator of Fig. 2 per step), or,
  * for method RK4, the classical four-stage Runge-Kutta scheme applied to the
@@ -275,26 +415,27 @@ static void save_observable(int32_t observable, int32_t n, const double* X, doub
  * scheme the paper names as its next stochastic method (Sec. 1.5, Sec. 4):
  * the Euler-Maruyama increment plus (1/2) g_ii dg_ii/dX_i ((dW_i)^2 - dt)
  * with dW_i = sqrt(dt) N_i, for diagonal noise (Kloeden & Platen, Numerical
- * Solution of SDEs, Sec. 10.3).  The state is observed every `stride` steps, the host
- * loop of Sec. 2.1.4 (Eq. 4) with s = stride.
+ * Solution of SDEs, Sec. 10.3), or, for IMPLICIT_EULER / IMPLICIT_MIDPOINT,
+ * implicit_step above on the ODE limit.  The state is observed every
+ * `stride` steps, the host loop of Sec. 2.1.4 (Eq. 4) with s = stride.
  *
  *   X0  [orbits][n]    p  [orbits][d] (p_per_orbit = 1) or [d] (= 0)
  *   out [orbits][nsteps/stride + 1][q], q = n (state) or 1 (Kuramoto r)
  *   orbit id of orbit o = orbit_ids[o], else orbit_offset + o;
  *   seed of orbit o     = orbit_seeds[o], else seed.
  * Returns 0, or -1 for an argument error.                                    */
-int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
-                     const double* X0, const double* p, int32_t p_per_orbit,
-                     int64_t orbits, double t0, double dt, int64_t nsteps, int64_t stride,
-                     uint64_t seed, uint64_t orbit_offset, uint64_t step_offset,
-                     const uint32_t* orbit_ids, const uint64_t* orbit_seeds,
-                     int32_t method, int32_t observable, double* out)
+static int integrate_system(const struct oracle_system* sys, const double* X0, const double* p,
+                            int32_t p_per_orbit, int64_t orbits, double t0, double dt,
+                            int64_t nsteps, int64_t stride, uint64_t seed, uint64_t orbit_offset,
+                            uint64_t step_offset, const uint32_t* orbit_ids,
+                            const uint64_t* orbit_seeds, int32_t method, int32_t observable,
+                            double* out)
 {
-    if (!oracle_model_dims_ok(model, n, m, d) || orbits < 0 || nsteps < 0 || stride < 1 ||
-        nsteps % stride != 0 ||
-        (method != METHOD_EM && method != METHOD_RK4 && method != METHOD_MILSTEIN))
+    const int32_t n = sys->n, m = sys->m, d = sys->d;
+    if (orbits < 0 || nsteps < 0 || stride < 1 || nsteps % stride != 0 || method < METHOD_EM ||
+        method > METHOD_IMPLICIT_MIDPOINT)
         return -1;
-    if (observable == OBS_KURAMOTO_R && model != M_KURAMOTO)
+    if (observable == OBS_KURAMOTO_R && sys->model != M_KURAMOTO)
         return -1;
     if (step_offset + (uint64_t)nsteps > 4294967296ull)
         return -1;
@@ -303,13 +444,14 @@ int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
     double* X = (double*)malloc(sizeof(double) * (size_t)n);
     double* f = (double*)malloc(sizeof(double) * (size_t)n);
     double* gx = (double*)malloc(sizeof(double) * (size_t)n);
-    double* xi = (double*)malloc(sizeof(double) * (size_t)m);
+    double* xi = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
     double* k1 = (double*)malloc(sizeof(double) * (size_t)n);
     double* k2 = (double*)malloc(sizeof(double) * (size_t)n);
     double* k3 = (double*)malloc(sizeof(double) * (size_t)n);
     double* k4 = (double*)malloc(sizeof(double) * (size_t)n);
     double* Y = (double*)malloc(sizeof(double) * (size_t)n);
     double* c = (double*)malloc(sizeof(double) * (size_t)n);
+    double* A = (double*)malloc(sizeof(double) * (size_t)n * (size_t)n);
     const double sqdt = sqrt(dt);
 
     for (int64_t o = 0; o < orbits; ++o) {
@@ -323,11 +465,11 @@ int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
         for (int64_t k = 0; k < nsteps; ++k) {
             double t = t0 + (double)k * dt;
             if (method == METHOD_EM || method == METHOD_MILSTEIN) {
-                oracle_drift(model, n, m, d, t, X, po, f);
+                sys_drift(sys, t, X, po, f);
                 oracle_normals(sd, id, (uint32_t)(step_offset + (uint64_t)k), m, xi);
-                oracle_diffusion(model, n, m, d, t, X, po, xi, gx);
+                sys_diffusion(sys, t, X, po, xi, gx);
                 if (method == METHOD_MILSTEIN)
-                    oracle_diffusion_dgdx(model, n, m, d, t, X, po, c);
+                    sys_dgdx(sys, t, X, po, c);
                 for (int32_t i = 0; i < n; ++i)
                     X[i] = X[i] + f[i] * dt + gx[i] * sqdt;
                 if (method == METHOD_MILSTEIN) {
@@ -336,27 +478,65 @@ int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
                         X[i] = X[i] + 0.5 * c[i] * (dW * dW - dt);
                     }
                 }
-            } else {
-                oracle_drift(model, n, m, d, t, X, po, k1);
+            } else if (method == METHOD_RK4) {
+                sys_drift(sys, t, X, po, k1);
                 for (int32_t i = 0; i < n; ++i)
                     Y[i] = X[i] + 0.5 * dt * k1[i];
-                oracle_drift(model, n, m, d, t + 0.5 * dt, Y, po, k2);
+                sys_drift(sys, t + 0.5 * dt, Y, po, k2);
                 for (int32_t i = 0; i < n; ++i)
                     Y[i] = X[i] + 0.5 * dt * k2[i];
-                oracle_drift(model, n, m, d, t + 0.5 * dt, Y, po, k3);
+                sys_drift(sys, t + 0.5 * dt, Y, po, k3);
                 for (int32_t i = 0; i < n; ++i)
                     Y[i] = X[i] + dt * k3[i];
-                oracle_drift(model, n, m, d, t + dt, Y, po, k4);
+                sys_drift(sys, t + dt, Y, po, k4);
                 for (int32_t i = 0; i < n; ++i)
                     X[i] = X[i] + (dt / 6.0) * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+            } else {
+                const double cc = method == METHOD_IMPLICIT_EULER ? 1.0 : 0.5;
+                implicit_step(sys, t, dt, cc, po, X, Y, k1, k2, k3, A, k4);
             }
             if ((k + 1) % stride == 0)
                 save_observable(observable, n, X, out_o + (size_t)((k + 1) / stride) * (size_t)q);
         }
     }
     free(X); free(f); free(gx); free(xi);
-    free(k1); free(k2); free(k3); free(k4); free(Y); free(c);
+    free(k1); free(k2); free(k3); free(k4); free(Y); free(c); free(A);
     return 0;
+}
+
+int oracle_integrate(int32_t model, int32_t n, int32_t m, int32_t d,
+                     const double* X0, const double* p, int32_t p_per_orbit,
+                     int64_t orbits, double t0, double dt, int64_t nsteps, int64_t stride,
+                     uint64_t seed, uint64_t orbit_offset, uint64_t step_offset,
+                     const uint32_t* orbit_ids, const uint64_t* orbit_seeds,
+                     int32_t method, int32_t observable, double* out)
+{
+    if (!oracle_model_dims_ok(model, n, m, d))
+        return -1;
+    struct oracle_system sys = {model, n, m, d, NULL, NULL};
+    return integrate_system(&sys, X0, p, p_per_orbit, orbits, t0, dt, nsteps, stride, seed,
+                            orbit_offset, step_offset, orbit_ids, orbit_seeds, method, observable,
+                            out);
+}
+
+/* The same integrator for a model given as two C functions (the analogue of
+ * the user-written system functions the paper compiles at run time,
+ * Sec. 2.1.3 and Fig. 5): drift(t, X, p, f) and diffusion(t, X, p, xi, gx),
+ * the latter returning sum_j g_ij xi_j without sqrt(dt).  Milstein treats
+ * such a model as having state-independent noise.                            */
+int oracle_integrate_custom(int32_t n, int32_t m, int32_t d, drift_cb drift,
+                            diffusion_cb diffusion, const double* X0, const double* p,
+                            int32_t p_per_orbit, int64_t orbits, double t0, double dt,
+                            int64_t nsteps, int64_t stride, uint64_t seed, uint64_t orbit_offset,
+                            uint64_t step_offset, const uint32_t* orbit_ids,
+                            const uint64_t* orbit_seeds, int32_t method, double* out)
+{
+    if (n < 1 || m < 0 || d < 0 || !drift || (m > 0 && !diffusion))
+        return -1;
+    struct oracle_system sys = {-1, n, m, d, drift, diffusion};
+    return integrate_system(&sys, X0, p, p_per_orbit, orbits, t0, dt, nsteps, stride, seed,
+                            orbit_offset, step_offset, orbit_ids, orbit_seeds, method, OBS_STATE,
+                            out);
 }
 
 /* ------------------------------------------------------------------------ */

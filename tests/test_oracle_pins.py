@@ -241,11 +241,15 @@ def _circ(x, y):
 
 
 @pytest.mark.parametrize("method,dts,order", [("em", (2e-2, 1e-2, 5e-3), 1.0),
-                                              ("rk4", (0.1, 0.05, 0.025), 4.0)])
+                                              ("rk4", (0.1, 0.05, 0.025), 4.0),
+                                              ("implicit_euler", (2e-2, 1e-2, 5e-3), 1.0),
+                                              ("implicit_midpoint", (0.1, 0.05, 0.025), 2.0)])
 def test_kuramoto_two_oscillators_adler(oracle_lib, method, dts, order):
     """n = 2, g = 0: psi = theta_2 - theta_1 obeys the Adler equation
     psi' = (omega_2 - omega_1) - K sin psi and theta_1 + theta_2 grows at
-    omega_1 + omega_2.  Euler converges with order 1, RK4 with order 4."""
+    omega_1 + omega_2 (a linear invariant every Runge-Kutta method keeps).
+    Euler, explicit or implicit, converges with order 1, the implicit
+    midpoint rule with order 2, RK4 with order 4."""
     K, w1, w2, T = 3.0, -2.0, 2.0, 2.0
     th0 = np.array([[0.4, 0.7]])
     p = workloads.kuramoto_params([K], [[w1, w2]], [[0.0, 0.0]])[0]
@@ -261,6 +265,33 @@ def test_kuramoto_two_oscillators_adler(oracle_lib, method, dts, order):
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     for r in rates:
         assert abs(r - order) < 0.1 * order, (rates, errs)
+
+
+@pytest.mark.parametrize("method", ["implicit_euler", "implicit_midpoint"])
+def test_implicit_steps_on_a_stiff_linear_decay(oracle_lib, method):
+    """OU without noise, x' = -a (x - mu) with a dt = 10 (explicit Euler would
+    diverge): implicit Euler multiplies x - mu by 1 / (1 + a dt) per step,
+    the midpoint rule by (1 - a dt / 2) / (1 + a dt / 2)."""
+    a, mu, dt, K = 1000.0, 0.3, 0.01, 40
+    X0 = np.array([[1.7], [-2.0], [0.3]])
+    out = oracle_lib.integrate("ou", 1, 1, 3, X0, [a, mu, 0.5], 0.0, dt, K, 1, 4, method=method)
+    z = a * dt
+    rho = 1.0 / (1.0 + z) if method == "implicit_euler" else (1.0 - z / 2) / (1.0 + z / 2)
+    want = mu + (X0[:, 0:1] - mu) * rho ** np.arange(K + 1)[None, :]
+    np.testing.assert_allclose(out[:, :, 0], want, rtol=0, atol=2e-14)
+
+
+@pytest.mark.parametrize("method,c", [("implicit_euler", 1.0), ("implicit_midpoint", 0.5)])
+def test_implicit_steps_solve_their_equation(oracle_lib, method, c):
+    """FHN chain (nonlinear, coupled): every saved step satisfies
+    Y = X + dt f(X + c (Y - X)) with f the separately pinned drift."""
+    n, p, dt = 6, np.array([0.7, 0.8, 0.08, 0.1, 0.05]), 0.05
+    X0 = np.array([[-1.0, 0.5, 1.2, -0.3, 0.2, 0.1]])
+    out = oracle_lib.integrate("fhn", n, 3, 5, X0, p, 0.0, dt, 30, 1, 4, method=method)[0]
+    for k in range(30):
+        X, Y = out[k], out[k + 1]
+        f = oracle_lib.drift("fhn", n, 3, 5, X + c * (Y - X), p)
+        np.testing.assert_allclose(Y, X + dt * f, rtol=0, atol=1e-13)
 
 
 # --------------------------------------------------------------------------- drifts
