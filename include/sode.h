@@ -96,7 +96,15 @@ int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out)
  *                      diagonal noise: the EM increment plus
  *                      (1/2) g_ii dg_ii/dX_i ((dW_i)^2 - dt).  Plain kernel
  *                      only; for models whose diffusion does not depend on
- *                      the state (all but "gbm") it equals EM exactly.
+ *                      the state (all but "gbm") it equals EM exactly;
+ *                  3 = implicit Euler, 4 = implicit midpoint rule, on the
+ *                      ODE limit g = 0 (the implicit solvers of Sec. 1.5):
+ *                      Y = X + dt f(t + c dt, X + c (Y - X)), c = 1 or 1/2,
+ *                      solved per step by Newton's method with a
+ *                      forward-difference Jacobian, stopping at a largest
+ *                      correction of 64 eps (1 + max|Y|) or after 50
+ *                      iterations.  Plain kernel only, n <= 16 (each lane
+ *                      holds an n x n matrix).
  *   "observable"   0 = state (q = n values per save);
  *                  1 = Kuramoto order parameter r of Eq. (7), Sec. 2.3.1
  *                      (q = 1; Kuramoto only).

@@ -14,7 +14,7 @@ __all__ = ["abi", "Integrator", "SodeError", "check", "OPTION_VALUES", "Kuramoto
            "RaggedBatch"]
 
 OPTION_VALUES = {
-    "method": {"em": 0, "rk4": 1, "milstein": 2},
+    "method": {"em": 0, "rk4": 1, "milstein": 2, "implicit_euler": 3, "implicit_midpoint": 4},
     "observable": {"state": 0, "kuramoto_r": 1},
     "kernel": {"auto": 0, "plain": 1, "coupled": 2, "matrix": 3},
     "gemm": {"bf16": 0, "bf16x3": 1, "fp32": 2},

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsode.so")
 
-SOURCES = ["sode_abi.cpp", "ragged_host.cpp", "plain.hip", "kuramoto_coupled.hip",
+SOURCES = ["sode_abi.cpp", "ragged_host.cpp", "plain.hip", "plain_implicit.hip", "kuramoto_coupled.hip",
            "kuramoto_adjoint.hip", "fhn_ragged.hip", "rnn_mfma.hip",
            "stats.hip"]
 

@@ -6,13 +6,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kinds.hpp"
 #include "sode.h"
 
 namespace sode {
-
-enum ModelId : int { kKuramoto = 0, kOU = 1, kGBM = 2, kFHN = 3, kRNN = 4 };
-enum MethodId : int { kEM = 0, kRK4 = 1, kMilstein = 2 };
-enum ObservableId : int { kState = 0, kKuramotoR = 1 };
 
 // One integrate request, already checked for shape and range.
 struct Request {
@@ -42,6 +39,10 @@ constexpr int kPlainMaxN = 128;
 // one work-item per orbit).  Returns a hipError_t.
 hipError_t launch_plain_f64(const Request& r);
 hipError_t launch_plain_f32(const Request& r);
+// Implicit Euler / implicit midpoint on the ODE limit, n <= kImplicitMaxN
+// (plain_implicit.hip; reached through the two launchers above).
+hipError_t launch_plain_implicit_f64(const Request& r);
+hipError_t launch_plain_implicit_f32(const Request& r);
 
 // Kuramoto, binary32, Euler-Maruyama: 16 lanes per orbit, any n <= 128
 // (sizes that are not multiples of 16 run padded).  The checkpointed forward

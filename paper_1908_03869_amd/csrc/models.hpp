@@ -1,13 +1,13 @@
 // models.hpp - drift and diffusion functors of the built-in SDE models.
 //
 // Each model supplies, for one orbit held in a per-lane array,
-//   drift(n, p, y, f)        f_i(t, X, p) of Eq. (1)  (all models here are
-//                            autonomous, so t is not an argument);
-//   diffuse(n, p, y, xi)     overwrites xi with sum_j g_ij xi_j (diagonal
+//   drift(n, t, p, y, f)     f_i(t, X, p) of Eq. (1) (the built-in models are
+//                            autonomous and ignore t);
+//   diffuse(n, t, p, y, xi)  overwrites xi with sum_j g_ij xi_j (diagonal
 //                            noise: g_ij = 0 for i != j), without sqrt(dt);
 //   noises(n)                m, the number of Wiener processes;
 //   kStateNoise              whether g depends on the state; if it does,
-//   dgdx(n, p, y, c)         c_i = g_ii dg_ii/dX_i, the coefficient of the
+//   dgdx(n, t, p, y, c)      c_i = g_ii dg_ii/dX_i, the coefficient of the
 //                            Milstein correction (diagonal noise with g_ii a
 //                            function of X_i alone).
 // These are the two user functions of the paper's per-step integrator
@@ -15,18 +15,9 @@
 // assembled into a runtime-compiled source string.
 #pragma once
 
-#include <hip/hip_runtime.h>
+#include "devmath.hpp"
 
 namespace sode {
-
-__device__ __forceinline__ float dev_sin(float x) { return sinf(x); }
-__device__ __forceinline__ double dev_sin(double x) { return sin(x); }
-__device__ __forceinline__ float dev_cos(float x) { return cosf(x); }
-__device__ __forceinline__ double dev_cos(double x) { return cos(x); }
-__device__ __forceinline__ float dev_tanh(float x) { return tanhf(x); }
-__device__ __forceinline__ double dev_tanh(double x) { return tanh(x); }
-__device__ __forceinline__ float dev_sqrt(float x) { return sqrtf(x); }
-__device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
 
 // Stochastic Kuramoto network, Eq. (5)/(6) of Sec. 2.2.1 with the
 // parameter layout p = (K, omega_1..N, p_1..N) of that section's footnote:
@@ -36,7 +27,7 @@ struct Kuramoto {
     static constexpr int kId = 0;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>
-    __device__ static void drift(int n, const R* __restrict__ p, const R* y, R* f)
+    __device__ static void drift(int n, R, const R* __restrict__ p, const R* y, R* f)
     {
         const R scale = p[0] / (R)n;
         for (int i = 0; i < n; ++i) {
@@ -48,7 +39,7 @@ struct Kuramoto {
         }
     }
     template <typename R>
-    __device__ static void diffuse(int n, const R* __restrict__ p, const R*, R* xi)
+    __device__ static void diffuse(int n, R, const R* __restrict__ p, const R*, R* xi)
     {
         for (int i = 0; i < n; ++i)
             xi[i] = p[n + 1 + i] * xi[i];
@@ -65,7 +56,7 @@ struct KuramotoMeanField {
     static constexpr int kId = 0;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>
-    __device__ static void drift(int n, const R* __restrict__ p, const R* y, R* f)
+    __device__ static void drift(int n, R, const R* __restrict__ p, const R* y, R* f)
     {
         R C = 0, S = 0;
         for (int j = 0; j < n; ++j) {
@@ -79,9 +70,9 @@ struct KuramotoMeanField {
         }
     }
     template <typename R>
-    __device__ static void diffuse(int n, const R* __restrict__ p, const R* y, R* xi)
+    __device__ static void diffuse(int n, R t, const R* __restrict__ p, const R* y, R* xi)
     {
-        Kuramoto::diffuse(n, p, y, xi);
+        Kuramoto::diffuse(n, t, p, y, xi);
     }
 };
 
@@ -91,13 +82,13 @@ struct OrnsteinUhlenbeck {
     static constexpr int kId = 1;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>
-    __device__ static void drift(int n, const R* __restrict__ p, const R* y, R* f)
+    __device__ static void drift(int n, R, const R* __restrict__ p, const R* y, R* f)
     {
         for (int i = 0; i < n; ++i)
             f[i] = -p[0] * (y[i] - p[1]);
     }
     template <typename R>
-    __device__ static void diffuse(int n, const R* __restrict__ p, const R*, R* xi)
+    __device__ static void diffuse(int n, R, const R* __restrict__ p, const R*, R* xi)
     {
         for (int i = 0; i < n; ++i)
             xi[i] = p[2] * xi[i];
@@ -110,19 +101,19 @@ struct GeometricBM {
     static constexpr int kId = 2;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>
-    __device__ static void drift(int n, const R* __restrict__ p, const R* y, R* f)
+    __device__ static void drift(int n, R, const R* __restrict__ p, const R* y, R* f)
     {
         for (int i = 0; i < n; ++i)
             f[i] = p[0] * y[i];
     }
     template <typename R>
-    __device__ static void diffuse(int n, const R* __restrict__ p, const R* y, R* xi)
+    __device__ static void diffuse(int n, R, const R* __restrict__ p, const R* y, R* xi)
     {
         for (int i = 0; i < n; ++i)
             xi[i] = p[1] * y[i] * xi[i];
     }
     template <typename R>
-    __device__ static void dgdx(int n, const R* __restrict__ p, const R* y, R* c)
+    __device__ static void dgdx(int n, R, const R* __restrict__ p, const R* y, R* c)
     {
         for (int i = 0; i < n; ++i)
             c[i] = (p[1] * y[i]) * p[1];
@@ -139,7 +130,7 @@ struct FhnChain {
     static constexpr int kId = 3;
     __host__ __device__ static constexpr int noises(int n) { return n / 2; }
     template <typename R>
-    __device__ static void drift(int n, const R* __restrict__ p, const R* y, R* f)
+    __device__ static void drift(int n, R, const R* __restrict__ p, const R* y, R* f)
     {
         const int N = n / 2;
         const R a = p[0], b = p[1], eps = p[2], D = p[3];
@@ -152,7 +143,7 @@ struct FhnChain {
         }
     }
     template <typename R>
-    __device__ static void diffuse(int n, const R* __restrict__ p, const R*, R* xi)
+    __device__ static void diffuse(int n, R, const R* __restrict__ p, const R*, R* xi)
     {
         const int N = n / 2;
         for (int i = 0; i < N; ++i)
@@ -169,7 +160,7 @@ struct DenseRnn {
     static constexpr int kId = 4;
     __host__ __device__ static constexpr int noises(int n) { return n; }
     template <typename R>
-    __device__ static void drift(int n, const R* __restrict__ p, const R* y, R* f)
+    __device__ static void drift(int n, R, const R* __restrict__ p, const R* y, R* f)
     {
         const R* W = p;
         const R* bias = p + (size_t)n * n;
@@ -181,7 +172,7 @@ struct DenseRnn {
         }
     }
     template <typename R>
-    __device__ static void diffuse(int n, const R* __restrict__ p, const R*, R* xi)
+    __device__ static void diffuse(int n, R, const R* __restrict__ p, const R*, R* xi)
     {
         const R sigma = p[(size_t)n * n + n];
         for (int i = 0; i < n; ++i)

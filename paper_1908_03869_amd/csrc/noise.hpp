@@ -9,7 +9,9 @@
 // so every orbit and step can be regenerated anywhere without stored state.
 #pragma once
 
+#ifndef __HIPCC_RTC__  // the run-time compiler provides the HIP runtime itself
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 namespace sode {

@@ -1,0 +1,237 @@
+// plain_kernel.hpp - the one-orbit-per-lane stepper, shared by the built-in
+// models (plain.hip) and by models given as source text, which are compiled
+// at run time against this same header (rtc.cpp).
+//
+// This is the paper's own mapping (Sec. 2.1.3, Step 2, Fig. 1: one work-item
+// integrates one orbit with private state arrays) written for gfx950.  All
+// steps run inside one launch and every saved state goes straight to HBM
+// (unlike the host loop of Sec. 2.1.4).
+#pragma once
+
+#include "devmath.hpp"
+#include "kinds.hpp"
+#include "noise.hpp"
+
+namespace sode {
+
+template <typename R>
+struct PlainArgs {
+    const R* __restrict__ X0;
+    const R* __restrict__ p;
+    R* __restrict__ out;
+    const uint32_t* __restrict__ ids;
+    const uint64_t* __restrict__ seeds;
+    int n, m, d, p_per_orbit, observable;
+    int64_t orbits, stride, nsave;
+    R t0, dt, sqdt;
+    uint64_t seed, orbit_offset, step_offset;
+};
+
+template <typename R>
+__device__ __forceinline__ R plain_order_parameter(int n, const R* y)
+{
+    R c = 0, s = 0;
+    for (int j = 0; j < n; ++j) {
+        c += dev_cos(y[j]);
+        s += dev_sin(y[j]);
+    }
+    return dev_sqrt(c * c + s * s) / (R)n;
+}
+
+template <typename R>
+__device__ __forceinline__ void plain_save(const PlainArgs<R>& a, int n, const R* y, R* dst)
+{
+    if (a.observable == kKuramotoR) {
+        dst[0] = plain_order_parameter(n, y);
+    } else {
+        for (int i = 0; i < n; ++i)
+            dst[i] = y[i];
+    }
+}
+
+template <typename R>
+struct Eps;
+template <>
+struct Eps<double> {
+    static constexpr double value = 0x1p-52;
+};
+template <>
+struct Eps<float> {
+    static constexpr float value = 0x1p-23f;
+};
+
+// Solve A x = b in place (A is n x n row-major with row pitch C; b becomes
+// x) by Gaussian elimination with partial pivoting.
+template <typename R, int C>
+__device__ __forceinline__ void solve_dense(int n, R* A, R* b)
+{
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (dev_fabs(A[r * C + col]) > dev_fabs(A[piv * C + col]))
+                piv = r;
+        if (piv != col) {
+            for (int c = 0; c < n; ++c) {
+                const R tmp = A[col * C + c];
+                A[col * C + c] = A[piv * C + c];
+                A[piv * C + c] = tmp;
+            }
+            const R tb = b[col];
+            b[col] = b[piv];
+            b[piv] = tb;
+        }
+        for (int r = col + 1; r < n; ++r) {
+            const R l = A[r * C + col] / A[col * C + col];
+            for (int c = col; c < n; ++c)
+                A[r * C + c] = A[r * C + c] - l * A[col * C + c];
+            b[r] = b[r] - l * b[col];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        R acc = b[r];
+        for (int c = r + 1; c < n; ++c)
+            acc = acc - A[r * C + c] * b[c];
+        b[r] = acc / A[r * C + r];
+    }
+}
+
+// One step of a one-stage implicit Runge-Kutta method on the ODE limit
+// g = 0 (the implicit solvers of Sec. 1.5; the implicit midpoint rule is the
+// one the authors' earlier stiff-model work used, Sec. 3):
+//     Y = X + dt f(t + c dt, X + c (Y - X)),
+// c = 1 implicit Euler, c = 1/2 implicit midpoint.  Newton's method on
+// G(Y) = Y - X - dt f(t + c dt, Z), Z = X + c (Y - X), from the explicit
+// Euler predictor; the Jacobian of f at Z by forward differences with step
+// sqrt(eps) max(1, |Z_j|) (the step actually taken is re-read from the
+// rounded Z_j + h); stop when the largest correction is at most
+// 64 eps (1 + max |Y|) or after 50 iterations (every lane exits).
+template <class Model, typename R, int C>
+__device__ __forceinline__ void implicit_step(int n, R t, R dt, R c, const R* __restrict__ p, R* X)
+{
+    const R eps = Eps<R>::value;
+    const R sqeps = dev_sqrt(eps);
+    R Y[C], Z[C], fz[C], fh[C], delta[C], A[C * C];
+    Model::drift(n, t, p, X, fz);
+    for (int i = 0; i < n; ++i)
+        Y[i] = X[i] + dt * fz[i];
+    const R ts = t + c * dt;
+    for (int it = 0; it < 50; ++it) {
+        for (int i = 0; i < n; ++i)
+            Z[i] = X[i] + c * (Y[i] - X[i]);
+        Model::drift(n, ts, p, Z, fz);
+        for (int j = 0; j < n; ++j) {
+            const R zj = Z[j];
+            R h = sqeps * (dev_fabs(zj) > (R)1 ? dev_fabs(zj) : (R)1);
+            Z[j] = zj + h;
+            h = Z[j] - zj;
+            Model::drift(n, ts, p, Z, fh);
+            Z[j] = zj;
+            for (int i = 0; i < n; ++i)
+                A[i * C + j] = (i == j ? (R)1 : (R)0) - c * dt * ((fh[i] - fz[i]) / h);
+        }
+        for (int i = 0; i < n; ++i)
+            delta[i] = -(Y[i] - X[i] - dt * fz[i]);
+        solve_dense<R, C>(n, A, delta);
+        R dmax = 0, ymax = 0;
+        for (int i = 0; i < n; ++i) {
+            Y[i] = Y[i] + delta[i];
+            dmax = dev_fabs(delta[i]) > dmax ? dev_fabs(delta[i]) : dmax;
+            ymax = dev_fabs(Y[i]) > ymax ? dev_fabs(Y[i]) : ymax;
+        }
+        if (dmax <= (R)64 * eps * ((R)1 + ymax))
+            break;
+    }
+    for (int i = 0; i < n; ++i)
+        X[i] = Y[i];
+}
+
+// Body of the one-orbit-per-lane kernel (64-lane blocks).  NC > 0: the state
+// dimension is the compile-time constant NC; NC == 0: the runtime a.n (up to
+// kPlainMaxN, kImplicitMaxN for the implicit methods).  METH: Euler-Maruyama
+// (Eq. 2); Milstein for diagonal state-dependent noise (the order-one method
+// named as the next step in Sec. 1.5 and Sec. 4: the EM increment plus
+// (1/2) g_ii dg_ii/dX_i ((dW_i)^2 - dt), dW_i = sqrt(dt) xi_i); the classical
+// Runge-Kutta scheme on the drift alone (ODE limit); or an implicit step.
+// t_k = t0 + k dt with k the step within this call.
+template <class Model, typename R, int NC, int METH, int MAXN>
+__device__ __forceinline__ void plain_body(const PlainArgs<R>& a)
+{
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= a.orbits)
+        return;
+    constexpr int CAP = NC > 0 ? NC : MAXN;
+    constexpr int ICAP = NC > 0 ? NC : (MAXN < kImplicitMaxN ? MAXN : kImplicitMaxN);
+    const int n = NC > 0 ? NC : a.n;
+    const int m = a.m;
+    const int q = a.observable == kKuramotoR ? 1 : n;
+    const R* __restrict__ p = a.p + (a.p_per_orbit ? o * (int64_t)a.d : 0);
+    R* __restrict__ out = a.out + o * a.nsave * q;
+
+    R y[CAP];
+    for (int i = 0; i < n; ++i)
+        y[i] = a.X0[o * n + i];
+    plain_save(a, n, y, out);
+
+    const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
+    int64_t k = 0;
+    for (int64_t s = 1; s < a.nsave; ++s) {
+        for (int64_t kk = 0; kk < a.stride; ++kk, ++k) {
+            const R t = a.t0 + (R)k * a.dt;
+            if constexpr (METH == kEM) {
+                // Euler-Maruyama, Eq. (2): X += f dt + (G xi) sqrt(dt).
+                R f[CAP], xi[CAP];
+                Model::drift(n, t, p, y, f);
+                normals<R>(st, (uint32_t)(a.step_offset + (uint64_t)k), m, xi);
+                for (int j = m; j < n; ++j)
+                    xi[j] = 0;
+                Model::diffuse(n, t, p, y, xi);
+                for (int i = 0; i < n; ++i)
+                    y[i] = y[i] + f[i] * a.dt + xi[i] * a.sqdt;
+            } else if constexpr (METH == kMilstein) {
+                R f[CAP], xi[CAP], gxi[CAP], c[CAP];
+                Model::drift(n, t, p, y, f);
+                Model::dgdx(n, t, p, y, c);
+                normals<R>(st, (uint32_t)(a.step_offset + (uint64_t)k), m, xi);
+                for (int j = m; j < n; ++j)
+                    xi[j] = 0;
+                for (int i = 0; i < n; ++i)
+                    gxi[i] = xi[i];
+                Model::diffuse(n, t, p, y, gxi);
+                for (int i = 0; i < n; ++i) {
+                    const R dW = a.sqdt * xi[i];
+                    y[i] = y[i] + f[i] * a.dt + gxi[i] * a.sqdt;
+                    y[i] = y[i] + (R)0.5 * c[i] * (dW * dW - a.dt);
+                }
+            } else if constexpr (METH == kRK4) {
+                // Classical RK4 on dX = f dt.
+                R kst[CAP], ksum[CAP], yt[CAP];
+                const R h = a.dt, half = a.dt / (R)2;
+                Model::drift(n, t, p, y, kst);
+                for (int i = 0; i < n; ++i) {
+                    ksum[i] = kst[i];
+                    yt[i] = y[i] + half * kst[i];
+                }
+                Model::drift(n, t + half, p, yt, kst);
+                for (int i = 0; i < n; ++i) {
+                    ksum[i] += (R)2 * kst[i];
+                    yt[i] = y[i] + half * kst[i];
+                }
+                Model::drift(n, t + half, p, yt, kst);
+                for (int i = 0; i < n; ++i) {
+                    ksum[i] += (R)2 * kst[i];
+                    yt[i] = y[i] + h * kst[i];
+                }
+                Model::drift(n, t + h, p, yt, kst);
+                for (int i = 0; i < n; ++i)
+                    y[i] = y[i] + (h / (R)6) * (ksum[i] + kst[i]);
+            } else {
+                static_assert(METH == kImplicitEuler || METH == kImplicitMidpoint, "method");
+                const R c = METH == kImplicitEuler ? (R)1 : (R)0.5;
+                implicit_step<Model, R, ICAP>(n, t, a.dt, c, p, y);
+            }
+        }
+        plain_save(a, n, y, out + s * q);
+    }
+}
+
+}  // namespace sode

@@ -317,8 +317,8 @@ extern "C" int sode_integrate_ragged(sode_t h, const sode_instance_t* inst, int3
     if (!std::isfinite(t0) || !std::isfinite(dt) || !(dt > 0.0))
         return SODE_EINVAL;
     // FHN noise is additive, so Milstein steps are the Euler-Maruyama steps;
-    // the ODE-only RK4 has no ragged kernel.
-    if (h->model != kFHN || h->precision != 32 || h->method == kRK4)
+    // the ODE-only methods have no ragged kernel.
+    if (h->model != kFHN || h->precision != 32 || (h->method != kEM && h->method != kMilstein))
         return SODE_EUNSUPPORTED;
     if (count == 0)
         return SODE_OK;

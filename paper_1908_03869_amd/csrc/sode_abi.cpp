@@ -104,7 +104,8 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
                             h->method == sode::kEM && sode::coupled_supports(h->n);
     const bool matrix_ok = h->model == sode::kRNN && h->precision == 32 && h->method == sode::kEM &&
                            h->shared_params && sode::rnn_mfma_supports(h->n);
-    const bool plain_ok = h->n <= sode::kPlainMaxN;
+    const bool implicit = h->method == sode::kImplicitEuler || h->method == sode::kImplicitMidpoint;
+    const bool plain_ok = h->n <= (implicit ? sode::kImplicitMaxN : sode::kPlainMaxN);
     if (h->kernel == 3) {
         if (!matrix_ok)
             return SODE_EUNSUPPORTED;
@@ -179,7 +180,7 @@ int sode_set_option(sode_t h, const char* key, int64_t value)
             return SODE_EINVAL;
         h->precision = (int)value;
     } else if (std::strcmp(key, "method") == 0) {
-        if (value != sode::kEM && value != sode::kRK4 && value != sode::kMilstein)
+        if (value < sode::kEM || value > sode::kImplicitMidpoint)
             return SODE_EINVAL;
         h->method = (int)value;
     } else if (std::strcmp(key, "observable") == 0) {

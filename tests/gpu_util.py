@@ -11,7 +11,7 @@ import numpy as np
 
 import paper_1908_03869_amd as sode
 
-OPT = {"em": 0, "rk4": 1, "milstein": 2, "state": 0, "kuramoto_r": 1, "auto": 0, "plain": 1, "coupled": 2}
+OPT = {"em": 0, "rk4": 1, "milstein": 2, "implicit_euler": 3, "implicit_midpoint": 4, "state": 0, "kuramoto_r": 1, "auto": 0, "plain": 1, "coupled": 2}
 
 
 def log(msg: str) -> None:

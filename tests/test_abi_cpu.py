@@ -69,7 +69,7 @@ def test_options_round_trip_and_reject_unknown():
             assert abi.sode_set_option(h, key, val) == 0
             assert abi.sode_get_option(h, key) == (0, val)
         assert abi.sode_set_option(h, "precision", 16) == abi.SODE_EINVAL
-        assert abi.sode_set_option(h, "method", 3) == abi.SODE_EINVAL
+        assert abi.sode_set_option(h, "method", 5) == abi.SODE_EINVAL
         assert abi.sode_set_option(h, "kernel", 7) == abi.SODE_EINVAL
         assert abi.sode_set_option(h, "drift", 2) == abi.SODE_EINVAL
         assert abi.sode_set_option(h, "bogus", 1) == abi.SODE_EINVAL
@@ -129,6 +129,12 @@ def test_unsupported_kernel_requests():
     assert _call(h) == abi.SODE_EUNSUPPORTED
     abi.sode_destroy(h)
     st, h = abi.sode_create("ou", 200, 200, 3)  # beyond the plain kernel's 128 states
+    assert _call(h) == abi.SODE_EUNSUPPORTED
+    abi.sode_destroy(h)
+    st, h = abi.sode_create("ou", 17, 17, 3)
+    abi.sode_set_option(h, "method", 3)  # implicit steppers hold n x n per lane: n <= 16
+    assert _call(h) == abi.SODE_EUNSUPPORTED
+    abi.sode_set_option(h, "method", 4)
     assert _call(h) == abi.SODE_EUNSUPPORTED
     abi.sode_destroy(h)
     st, h = abi.sode_create("rnn", 256, 256, 256 * 256 + 257)
