@@ -71,6 +71,12 @@ def lib():
                ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
                ctypes.c_uint64, u32p, u64p, ctypes.c_int32, ctypes.c_int32, f64p])
         L.oracle_integrate.restype = ctypes.c_int
+        L.oracle_integrate_custom.argtypes = (
+            [ctypes.c_int32] * 3 + [ctypes.c_void_p, ctypes.c_void_p]
+            + [f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+               ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
+               ctypes.c_uint64, u32p, u64p, ctypes.c_int32, f64p])
+        L.oracle_integrate_custom.restype = ctypes.c_int
         L.oracle_kuramoto_adjoint.argtypes = [
             ctypes.c_int32, f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
             ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
@@ -133,11 +139,55 @@ def order_parameter(theta) -> float:
     return float(lib().oracle_order_parameter(theta.size, tp))
 
 
+_CUSTOM_TEMPLATE = """#include <math.h>
+typedef double real;
+void sode_user_drift(double t, const real* y, const real* p, real* f)
+{
+%s
+}
+void sode_user_diffusion(double t, const real* y, const real* p, const real* xi, real* gx)
+{
+%s
+}
+"""
+
+
+def custom_model(drift: str, diffusion: str | None, n: int):
+    """Compile a model given as the bodies of its two system functions (the
+    text a source-text library handle receives) as plain C with the oracle's
+    flags; returns (drift, diffusion) function addresses.  Cached by source."""
+    import hashlib
+    import tempfile
+    diff = diffusion if diffusion is not None else f"for (int i = 0; i < {n}; ++i) gx[i] = 0;"
+    src = _CUSTOM_TEMPLATE % (drift, diff)
+    key = hashlib.sha256(src.encode()).hexdigest()[:20]
+    if key not in _custom:
+        d = os.path.join(tempfile.gettempdir(), "sode_oracle_custom")
+        os.makedirs(d, exist_ok=True)
+        c_path = os.path.join(d, key + ".c")
+        so_path = os.path.join(d, key + ".so")
+        if not os.path.exists(so_path):
+            with open(c_path, "w") as f:
+                f.write(src)
+            tmp = so_path + f".{os.getpid()}.tmp"
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+                                   "-fPIC", "-shared", "-o", tmp, c_path, "-lm"])
+            os.replace(tmp, so_path)
+        so = ctypes.CDLL(so_path)
+        _custom[key] = (so, ctypes.cast(so.sode_user_drift, ctypes.c_void_p).value,
+                        ctypes.cast(so.sode_user_diffusion, ctypes.c_void_p).value)
+    return _custom[key][1], _custom[key][2]
+
+
+_custom = {}
+
+
 def integrate(model: str, n: int, m: int, d: int, X0, p, t0: float, dt: float, nsteps: int,
               stride: int, seed: int, *, method: str = "em", observable: str = "state",
               orbit_offset: int = 0, step_offset: int = 0, orbit_ids=None, orbit_seeds=None,
-              p_per_orbit: bool | None = None) -> np.ndarray:
-    """Integrate every orbit; returns out[orbits, nsteps/stride+1, q] in float64."""
+              p_per_orbit: bool | None = None, custom=None) -> np.ndarray:
+    """Integrate every orbit; returns out[orbits, nsteps/stride+1, q] in float64.
+    model "custom" takes custom = (drift body, diffusion body) source text."""
     X0, X0p = _f64(X0)
     X0 = X0.reshape(-1, n)
     orbits = X0.shape[0]
@@ -162,10 +212,17 @@ def integrate(model: str, n: int, m: int, d: int, X0, p, t0: float, dt: float, n
         seeds_arr = np.ascontiguousarray(orbit_seeds, dtype=np.uint64)
         assert seeds_arr.size == orbits
         seeds_p = seeds_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
-    rc = lib().oracle_integrate(
-        MODELS[model], n, m, d, X0p, pp, int(bool(p_per_orbit)), orbits, t0, dt, nsteps, stride,
-        seed, orbit_offset, step_offset, ids_p, seeds_p, METHODS[method], OBSERVABLES[observable],
-        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if model == "custom":
+        fd, fg = custom_model(custom[0], custom[1], n)
+        rc = lib().oracle_integrate_custom(
+            n, m, d, ctypes.c_void_p(fd), ctypes.c_void_p(fg), X0p, pp, int(bool(p_per_orbit)),
+            orbits, t0, dt, nsteps, stride, seed, orbit_offset, step_offset, ids_p, seeds_p,
+            METHODS[method], out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    else:
+        rc = lib().oracle_integrate(
+            MODELS[model], n, m, d, X0p, pp, int(bool(p_per_orbit)), orbits, t0, dt, nsteps,
+            stride, seed, orbit_offset, step_offset, ids_p, seeds_p, METHODS[method],
+            OBSERVABLES[observable], out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if rc != 0:
         raise ValueError(f"oracle_integrate rejected its arguments (rc={rc})")
     return out
@@ -185,6 +242,8 @@ def integrate_parallel(model, n, m, d, X0, p, t0, dt, nsteps, stride, seed, *, t
     p = np.ascontiguousarray(p, dtype=np.float64)
     per = p.ndim == 2
     bounds = np.linspace(0, orbits, threads + 1).astype(int)
+    if model == "custom":  # compile the callbacks once, before the threads start
+        custom_model(kw["custom"][0], kw["custom"][1], n)
 
     def run(i):
         a, b = bounds[i], bounds[i + 1]

@@ -359,22 +359,23 @@ static void solve_dense(int32_t n, double* A, double* b)
  *     Y = X + dt f(t + c dt, X + c (Y - X)),
  * c = 1 for implicit Euler, c = 1/2 for the implicit midpoint rule.  Y is
  * found by Newton's method on G(Y) = Y - X - dt f(t + c dt, Z),
- * Z = X + c (Y - X), starting from the explicit Euler predictor; the
- * Jacobian of f at Z is formed by forward differences with step
- * sqrt(eps) max(1, |Z_j|), and each Newton system I - c dt J is solved by
- * Gaussian elimination with partial pivoting.  Iteration stops when the
- * largest correction is at most 64 eps (1 + max |Y|) (eps = 2^-52), or after
- * 50 iterations.  X is overwritten with Y.                                   */
+ * Z = X + c (Y - X), starting from Y = X (so the first iterate is the
+ * linearly implicit step, the usual start for stiff systems); the Jacobian
+ * of f at Z is formed by forward differences with step sqrt(eps) max(1,
+ * |Z_j|), and each Newton system I - c dt J is solved by Gaussian
+ * elimination with partial pivoting.  Iteration stops when the largest
+ * correction is at most 64 eps (1 + max |Y|) (eps = 2^-52).  X is
+ * overwritten with Y, or with NaN if 50 iterations did not converge.        */
 static void implicit_step(const struct oracle_system* s, double t, double dt, double c,
                           const double* p, double* X, double* Y, double* Z, double* fz,
                           double* fh, double* A, double* delta)
 {
     const int32_t n = s->n;
     const double eps = 0x1p-52;
-    sys_drift(s, t, X, p, fz);
     for (int32_t i = 0; i < n; ++i)
-        Y[i] = X[i] + dt * fz[i];
+        Y[i] = X[i];
     const double ts = t + c * dt;
+    int converged = 0;
     for (int32_t it = 0; it < 50; ++it) {
         for (int32_t i = 0; i < n; ++i)
             Z[i] = X[i] + c * (Y[i] - X[i]);
@@ -400,10 +401,13 @@ static void implicit_step(const struct oracle_system* s, double t, double dt, do
             if (fabs(Y[i]) > ymax)
                 ymax = fabs(Y[i]);
         }
-        if (dmax <= 64.0 * eps * (1.0 + ymax))
+        if (dmax <= 64.0 * eps * (1.0 + ymax)) {
+            converged = 1;
             break;
+        }
     }
-    memcpy(X, Y, sizeof(double) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i)
+        X[i] = converged ? Y[i] : NAN;
 }
 
 /* ------------------------------------------------------------------------ */

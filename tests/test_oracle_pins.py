@@ -496,3 +496,58 @@ def test_adjoint_uncoupled_closed_form(oracle_lib):
             dXdK += dt / n * np.array([np.sin(X - X[i]).sum() for i in range(n)])
             noise_sum += xi[k]
     np.testing.assert_allclose(grad, want, rtol=1e-10, atol=1e-13)
+
+
+# --------------------------------------------------------------------------- source-text models
+KURAMOTO4_DRIFT = """
+const int N = 4;
+for (int i = 0; i < N; ++i) {
+    real acc = 0;
+    for (int j = 0; j < N; ++j) acc = acc + sin(y[j] - y[i]);
+    f[i] = acc * (p[0] / N) + p[1 + i];
+}
+"""
+KURAMOTO4_DIFFUSION = "for (int i = 0; i < 4; ++i) gx[i] = p[5 + i] * xi[i];"
+
+
+@pytest.mark.parametrize("method", ["em", "rk4", "implicit_midpoint"])
+def test_custom_model_equals_builtin(oracle_lib, method):
+    """The Kuramoto system written as source text (as the paper's users write
+    it, Fig. 5) integrates bit for bit like the built-in model."""
+    w = workloads.kuramoto_small()
+    X0, p = w["X0"][:20], w["p"][:20]
+    a = oracle_lib.integrate("kuramoto", 4, 4, 9, X0, p, 0.0, 0.01, 300, 100, 7, method=method)
+    b = oracle_lib.integrate("custom", 4, 4, 9, X0, p, 0.0, 0.01, 300, 100, 7, method=method,
+                             custom=(KURAMOTO4_DRIFT, KURAMOTO4_DIFFUSION))
+    np.testing.assert_array_equal(a, b)
+
+
+def test_implicit_step_without_a_root_is_nan(oracle_lib):
+    """x' = x^2 + 1, dt = 0.1: from x = 100 the implicit Euler equation
+    0.1 Y^2 - Y + 100.1 = 0 has no real root, so Newton cannot converge and
+    the state becomes NaN; from x = 0 the root (1 - sqrt(0.96)) / 0.2 is found."""
+    out = oracle_lib.integrate("custom", 1, 0, 1, [[100.0], [0.0]], [0.0], 0.0, 0.1, 1, 1, 1,
+                               method="implicit_euler", custom=("f[0] = y[0] * y[0] + 1;", None))
+    assert np.isnan(out[0, 1, 0])
+    assert out[1, 1, 0] == pytest.approx((1 - math.sqrt(0.96)) / 0.2, rel=1e-13)
+
+
+def test_custom_model_time_argument(oracle_lib):
+    """dx = a t dt with t_k = t0 + k dt: Euler gives x_K = x0 + a dt (K t0 +
+    dt K (K - 1) / 2) exactly in real arithmetic."""
+    a, t0, dt, K = 0.5, 2.0, 0.125, 16
+    out = oracle_lib.integrate("custom", 1, 0, 1, [[1.0]], [a], t0, dt, K, K, 3,
+                               custom=("f[0] = p[0] * t;", None))
+    assert out[0, -1, 0] == pytest.approx(1.0 + a * dt * (K * t0 + dt * K * (K - 1) / 2), rel=1e-15)
+
+
+def test_custom_model_more_noises_than_equations(oracle_lib):
+    """n = 1, m = 2: dx = -x dt + s1 dW1 + s2 dW2, three steps by hand with the
+    step's first two normals."""
+    s1, s2, dt, x = 0.3, 0.7, 0.1, 1.5
+    out = oracle_lib.integrate("custom", 1, 2, 2, [[x]], [s1, s2], 0.0, dt, 3, 1, 11,
+                               custom=("f[0] = -y[0];", "gx[0] = p[0] * xi[0] + p[1] * xi[1];"))
+    for k in range(3):
+        xi = oracle_lib.normals(11, 0, k, 2)
+        x = x + (-x) * dt + (s1 * xi[0] + s2 * xi[1]) * math.sqrt(dt)
+        assert out[0, k + 1, 0] == x
