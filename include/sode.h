@@ -25,6 +25,7 @@
 #ifndef SODE_H
 #define SODE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -56,7 +57,8 @@ enum sode_status {
     SODE_ENOMEM = -2,       /* allocation of library-owned memory failed        */
     SODE_EDEVICE = -3,      /* a HIP call or a kernel launch failed             */
     SODE_EUNSUPPORTED = -4, /* valid request that this build does not implement */
-    SODE_ENONFINITE = -5    /* a saved state was NaN or infinite                */
+    SODE_ENONFINITE = -5,   /* a saved state was NaN or infinite                */
+    SODE_EBUILD = -6        /* run-time compilation of a model source failed    */
 };
 
 /*
@@ -84,6 +86,51 @@ enum sode_status {
 int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out);
 
 /*
+ * sode_create_custom - make a handle for a model given as source text: the
+ * bodies of its two system functions, as the paper's users write the drift
+ * and stochastic functions of their system (Sec. 2.1.3, Fig. 5) and the
+ * framework compiles them at run time.
+ *
+ *   drift_body      C/C++ statements that set f[0..n) from
+ *                       real t, const real* y, const real* p
+ *                   (real is float or double after the handle's precision);
+ *                   the device math functions (sin, cos, exp, tanh, sqrt,
+ *                   pow, fabs, ...) are available.
+ *   diffusion_body  statements that set gx[0..n) = sum_j g_ij(t, y, p) xi[j]
+ *                   from t, y, p and const real* xi (m normals), without
+ *                   sqrt(dt), which the stepper applies (Eq. 2).  May be
+ *                   NULL when m = 0 (an ODE).
+ *   n, m, d         1 <= n <= 128 equations, 0 <= m <= 128 Wiener
+ *                   processes, d >= 0 parameters per orbit (p must still
+ *                   be a valid pointer when d = 0).
+ * The texts are copied; nothing is compiled here (no HIP call is made).  The
+ * handle takes every option of sode_create's handles except observable r;
+ * it runs on the one-orbit-per-lane stepper with methods 0 (EM), 1 (RK4),
+ * 3 and 4 (implicit, n <= 16); method 2 gives SODE_EUNSUPPORTED (the
+ * diffusion's state derivative is not known).  Noise addressing, saves,
+ * sode_integrate_ex offsets and ids are those of the built-in models.
+ * Compilation (hipRTC, gfx950) happens in sode_build or on the first
+ * integrate call of each precision, and is cached per process by source.
+ * Returns SODE_EINVAL for a NULL drift body, a NULL diffusion body with
+ * m > 0 or sizes out of range.
+ */
+int sode_create_custom(const char* drift_body, const char* diffusion_body, int32_t n, int32_t m,
+                       int32_t d, sode_t* out);
+
+/*
+ * sode_build - compile a source-text handle for its current precision now
+ * (host work only: no GPU is needed).  SODE_OK, or SODE_EBUILD with the
+ * compiler's messages in sode_build_log (line numbers refer to the drift or
+ * diffusion body).  A handle of a built-in model returns SODE_OK.
+ *
+ * sode_build_log - copy the last compilation log into buf (at most len - 1
+ * bytes and a terminating NUL; buf may be NULL); *needed (if not NULL)
+ * receives the full length + 1.
+ */
+int sode_build(sode_t h);
+int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
+
+/*
  * sode_set_option / sode_get_option - integer options of a handle.
  *
  *   "precision"    32 | 64   arithmetic type of the state and of X0/p/out.
@@ -100,11 +147,12 @@ int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out)
  *                  3 = implicit Euler, 4 = implicit midpoint rule, on the
  *                      ODE limit g = 0 (the implicit solvers of Sec. 1.5):
  *                      Y = X + dt f(t + c dt, X + c (Y - X)), c = 1 or 1/2,
- *                      solved per step by Newton's method with a
- *                      forward-difference Jacobian, stopping at a largest
- *                      correction of 64 eps (1 + max|Y|) or after 50
- *                      iterations.  Plain kernel only, n <= 16 (each lane
- *                      holds an n x n matrix).
+ *                      solved per step by Newton's method from Y = X with
+ *                      a forward-difference Jacobian, stopping at a largest
+ *                      correction of 64 eps (1 + max|Y|); a step that has
+ *                      not converged after 50 iterations sets the state to
+ *                      NaN.  Plain kernel only, n <= 16 (each lane holds an
+ *                      n x n matrix).
  *   "observable"   0 = state (q = n values per save);
  *                  1 = Kuramoto order parameter r of Eq. (7), Sec. 2.3.1
  *                      (q = 1; Kuramoto only).

@@ -40,6 +40,33 @@ class Integrator:
         for k, v in options.items():
             self.set_option(k, v)
 
+    @classmethod
+    def custom(cls, drift: str, diffusion: str | None, n: int, m: int, d: int, **options):
+        """A handle for a model given as source text (sode_create_custom): the
+        bodies of drift(t, y, p) -> f[0..n) and diffusion(t, y, p, xi) ->
+        gx[0..n), compiled for gfx950 at run time."""
+        self = cls.__new__(cls)
+        st, h = abi.sode_create_custom(drift, diffusion, n, m, d)
+        check(st, f"sode_create_custom(n={n}, m={m}, d={d})")
+        self.handle = h
+        self.model, self.n, self.m, self.d = "custom", n, m, d
+        self.options = {"precision": 32, "method": 0, "observable": 0, "kernel": 0,
+                        "shared_params": 0, "compensated": 1, "waves_per_cu": 0,
+                        "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1, "drift": 0}
+        for k, v in options.items():
+            self.set_option(k, v)
+        return self
+
+    def build(self) -> None:
+        """Compile a source-text model now (sode_build); raises with the
+        compiler's log on failure."""
+        st = abi.sode_build(self.handle)
+        if st != abi.SODE_OK:
+            raise SodeError(st, "sode_build:\n" + self.build_log())
+
+    def build_log(self) -> str:
+        return abi.sode_build_log(self.handle)[1]
+
     def set_option(self, key: str, value) -> None:
         if isinstance(value, str):
             value = OPTION_VALUES[key][value]

@@ -19,10 +19,12 @@ SODE_ENOMEM = -2
 SODE_EDEVICE = -3
 SODE_EUNSUPPORTED = -4
 SODE_ENONFINITE = -5
+SODE_EBUILD = -6
 
 # Every symbol include/sode.h declares.
 EXPORTS = (
-    "sode_create", "sode_set_option", "sode_get_option", "sode_integrate",
+    "sode_create", "sode_create_custom", "sode_build", "sode_build_log",
+    "sode_set_option", "sode_get_option", "sode_integrate",
     "sode_integrate_ex", "sode_forward_ckpt", "sode_adjoint", "sode_integrate_ragged",
     "sode_ensemble_stats", "sode_sync", "sode_destroy", "sode_strerror", "sode_version",
 )
@@ -62,6 +64,14 @@ def load() -> ctypes.CDLL:
                               ctypes.c_uint64, ctypes.c_double)
     L.sode_create.argtypes = [ctypes.c_char_p, i32, i32, i32, ctypes.POINTER(vp)]
     L.sode_create.restype = ctypes.c_int
+    L.sode_create_custom.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i32, i32, i32,
+                                     ctypes.POINTER(vp)]
+    L.sode_create_custom.restype = ctypes.c_int
+    L.sode_build.argtypes = [vp]
+    L.sode_build.restype = ctypes.c_int
+    L.sode_build_log.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t,
+                                 ctypes.POINTER(ctypes.c_size_t)]
+    L.sode_build_log.restype = ctypes.c_int
     L.sode_set_option.argtypes = [vp, ctypes.c_char_p, i64]
     L.sode_set_option.restype = ctypes.c_int
     L.sode_get_option.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64)]
@@ -99,6 +109,29 @@ def sode_create(model: str, n: int, m: int, d: int):
     h = ctypes.c_void_p()
     st = load().sode_create(model.encode(), n, m, d, ctypes.byref(h))
     return st, h.value
+
+
+def sode_create_custom(drift_body: str, diffusion_body, n: int, m: int, d: int):
+    """Returns (status, handle) for a model given as source text."""
+    h = ctypes.c_void_p()
+    diff = None if diffusion_body is None else diffusion_body.encode()
+    st = load().sode_create_custom(drift_body.encode(), diff, n, m, d, ctypes.byref(h))
+    return st, h.value
+
+
+def sode_build(h) -> int:
+    return load().sode_build(h)
+
+
+def sode_build_log(h):
+    """Returns (status, text) of the last run-time compilation."""
+    need = ctypes.c_size_t()
+    st = load().sode_build_log(h, None, 0, ctypes.byref(need))
+    if st != SODE_OK:
+        return st, ""
+    buf = ctypes.create_string_buffer(need.value)
+    st = load().sode_build_log(h, buf, need.value, None)
+    return st, buf.value.decode(errors="replace")
 
 
 def sode_set_option(h, key: str, value: int) -> int:

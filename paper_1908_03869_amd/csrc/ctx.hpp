@@ -6,8 +6,13 @@
 #include <cstddef>
 #include <cstdint>
 #include <map>
+#include <string>
 
 #include "launch.hpp"
+
+namespace sode {
+struct RtcState;
+}
 
 struct sode_ctx {
     int model;
@@ -49,8 +54,18 @@ struct sode_ctx {
     hipGraphExec_t rg_exec = nullptr;
     uint64_t rg_graph_key = 0;
     hipStream_t rg_capture = nullptr;
+
+    // Model given as source text (model == kCustom): the two function
+    // bodies, the compiled code objects and loaded modules, the last log.
+    std::string drift_src, diffusion_src, build_log;
+    sode::RtcState* rtc = nullptr;
 };
 
 namespace sode {
 void release_ragged(sode_ctx* h);
+// Compile the handle's source-text model for a precision (no device needed).
+int rtc_build(sode_ctx* h, int precision);
+// Compile if needed, load on the current device and launch.
+int rtc_launch(sode_ctx* h, const Request& r, int precision);
+void rtc_release(sode_ctx* h);
 }

@@ -35,6 +35,13 @@ struct Request {
 // Largest state dimension of the one-orbit-per-lane kernel.
 constexpr int kPlainMaxN = 128;
 
+// Kernel arguments of the one-orbit-per-lane stepper (plain_kernel.hpp),
+// filled from a request (plain.hip).
+template <typename R>
+struct PlainArgs;
+template <typename R>
+PlainArgs<R> plain_args(const Request& r);
+
 // One orbit per lane, any model, binary64 or binary32 (the paper's design:
 // one work-item per orbit).  Returns a hipError_t.
 hipError_t launch_plain_f64(const Request& r);

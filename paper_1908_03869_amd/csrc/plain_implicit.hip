@@ -8,10 +8,6 @@
 #include "plain_kernel.hpp"
 
 namespace sode {
-
-template <typename R>
-PlainArgs<R> plain_args(const Request& r);
-
 namespace {
 
 template <class Model, typename R, int METH>

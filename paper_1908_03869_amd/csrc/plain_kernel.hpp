@@ -100,21 +100,22 @@ __device__ __forceinline__ void solve_dense(int n, R* A, R* b)
 // one the authors' earlier stiff-model work used, Sec. 3):
 //     Y = X + dt f(t + c dt, X + c (Y - X)),
 // c = 1 implicit Euler, c = 1/2 implicit midpoint.  Newton's method on
-// G(Y) = Y - X - dt f(t + c dt, Z), Z = X + c (Y - X), from the explicit
-// Euler predictor; the Jacobian of f at Z by forward differences with step
-// sqrt(eps) max(1, |Z_j|) (the step actually taken is re-read from the
-// rounded Z_j + h); stop when the largest correction is at most
-// 64 eps (1 + max |Y|) or after 50 iterations (every lane exits).
+// G(Y) = Y - X - dt f(t + c dt, Z), Z = X + c (Y - X), from Y = X (the first
+// iterate is the linearly implicit step); the Jacobian of f at Z by forward
+// differences with step sqrt(eps) max(1, |Z_j|) (the step actually taken is
+// re-read from the rounded Z_j + h); stop when the largest correction is at
+// most 64 eps (1 + max |Y|).  After 50 iterations without convergence the
+// state becomes NaN (every lane exits the loop).
 template <class Model, typename R, int C>
 __device__ __forceinline__ void implicit_step(int n, R t, R dt, R c, const R* __restrict__ p, R* X)
 {
     const R eps = Eps<R>::value;
     const R sqeps = dev_sqrt(eps);
     R Y[C], Z[C], fz[C], fh[C], delta[C], A[C * C];
-    Model::drift(n, t, p, X, fz);
     for (int i = 0; i < n; ++i)
-        Y[i] = X[i] + dt * fz[i];
+        Y[i] = X[i];
     const R ts = t + c * dt;
+    bool converged = false;
     for (int it = 0; it < 50; ++it) {
         for (int i = 0; i < n; ++i)
             Z[i] = X[i] + c * (Y[i] - X[i]);
@@ -138,11 +139,13 @@ __device__ __forceinline__ void implicit_step(int n, R t, R dt, R c, const R* __
             dmax = dev_fabs(delta[i]) > dmax ? dev_fabs(delta[i]) : dmax;
             ymax = dev_fabs(Y[i]) > ymax ? dev_fabs(Y[i]) : ymax;
         }
-        if (dmax <= (R)64 * eps * ((R)1 + ymax))
+        if (dmax <= (R)64 * eps * ((R)1 + ymax)) {
+            converged = true;
             break;
+        }
     }
     for (int i = 0; i < n; ++i)
-        X[i] = Y[i];
+        X[i] = converged ? Y[i] : __builtin_nan("");
 }
 
 // Body of the one-orbit-per-lane kernel (64-lane blocks).  NC > 0: the state
@@ -152,8 +155,10 @@ __device__ __forceinline__ void implicit_step(int n, R t, R dt, R c, const R* __
 // named as the next step in Sec. 1.5 and Sec. 4: the EM increment plus
 // (1/2) g_ii dg_ii/dX_i ((dW_i)^2 - dt), dW_i = sqrt(dt) xi_i); the classical
 // Runge-Kutta scheme on the drift alone (ODE limit); or an implicit step.
-// t_k = t0 + k dt with k the step within this call.
-template <class Model, typename R, int NC, int METH, int MAXN>
+// t_k = t0 + k dt with k the step within this call.  MC: capacity of the
+// noise array when a model has more Wiener processes than equations (0: the
+// state capacity).
+template <class Model, typename R, int NC, int METH, int MAXN, int MC = 0>
 __device__ __forceinline__ void plain_body(const PlainArgs<R>& a)
 {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -161,6 +166,7 @@ __device__ __forceinline__ void plain_body(const PlainArgs<R>& a)
         return;
     constexpr int CAP = NC > 0 ? NC : MAXN;
     constexpr int ICAP = NC > 0 ? NC : (MAXN < kImplicitMaxN ? MAXN : kImplicitMaxN);
+    constexpr int XCAP = MC > CAP ? MC : CAP;
     const int n = NC > 0 ? NC : a.n;
     const int m = a.m;
     const int q = a.observable == kKuramotoR ? 1 : n;
@@ -179,7 +185,7 @@ __device__ __forceinline__ void plain_body(const PlainArgs<R>& a)
             const R t = a.t0 + (R)k * a.dt;
             if constexpr (METH == kEM) {
                 // Euler-Maruyama, Eq. (2): X += f dt + (G xi) sqrt(dt).
-                R f[CAP], xi[CAP];
+                R f[CAP], xi[XCAP];
                 Model::drift(n, t, p, y, f);
                 normals<R>(st, (uint32_t)(a.step_offset + (uint64_t)k), m, xi);
                 for (int j = m; j < n; ++j)
@@ -188,13 +194,13 @@ __device__ __forceinline__ void plain_body(const PlainArgs<R>& a)
                 for (int i = 0; i < n; ++i)
                     y[i] = y[i] + f[i] * a.dt + xi[i] * a.sqdt;
             } else if constexpr (METH == kMilstein) {
-                R f[CAP], xi[CAP], gxi[CAP], c[CAP];
+                R f[CAP], xi[XCAP], gxi[XCAP], c[CAP];
                 Model::drift(n, t, p, y, f);
                 Model::dgdx(n, t, p, y, c);
                 normals<R>(st, (uint32_t)(a.step_offset + (uint64_t)k), m, xi);
                 for (int j = m; j < n; ++j)
                     xi[j] = 0;
-                for (int i = 0; i < n; ++i)
+                for (int i = 0; i < (m > n ? m : n); ++i)
                     gxi[i] = xi[i];
                 Model::diffuse(n, t, p, y, gxi);
                 for (int i = 0; i < n; ++i) {

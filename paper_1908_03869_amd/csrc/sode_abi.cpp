@@ -100,6 +100,15 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
 // between 40,960 and 81,920 orbits at n = 5).
 int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 {
+    if (h->model == sode::kCustom) {
+        // Source-text models run on the run-time compiled plain stepper.
+        const bool implicit = h->method == sode::kImplicitEuler || h->method == sode::kImplicitMidpoint;
+        if ((h->kernel != 0 && h->kernel != 1) || h->method == sode::kMilstein ||
+            (implicit && h->n > sode::kImplicitMaxN))
+            return SODE_EUNSUPPORTED;
+        *kernel = 4;
+        return SODE_OK;
+    }
     const bool coupled_ok = h->model == sode::kKuramoto && h->precision == 32 &&
                             h->method == sode::kEM && sode::coupled_supports(h->n);
     const bool matrix_ok = h->model == sode::kRNN && h->precision == 32 && h->method == sode::kEM &&
@@ -145,6 +154,7 @@ const char* sode_strerror(int status)
     case SODE_EDEVICE: return "HIP device or launch error";
     case SODE_EUNSUPPORTED: return "unsupported combination of model, size and options";
     case SODE_ENONFINITE: return "non-finite value in a saved state";
+    case SODE_EBUILD: return "run-time compilation of the model source failed (see sode_build_log)";
     default: return "unknown status";
     }
 }
@@ -168,6 +178,52 @@ int sode_create(const char* model, int32_t n, int32_t m, int32_t d, sode_t* out)
     h->m = m;
     h->d = d;
     *out = h;
+    return SODE_OK;
+}
+
+int sode_create_custom(const char* drift_body, const char* diffusion_body, int32_t n, int32_t m,
+                       int32_t d, sode_t* out)
+{
+    if (!out)
+        return SODE_EINVAL;
+    *out = nullptr;
+    if (!drift_body || (m > 0 && !diffusion_body))
+        return SODE_EINVAL;
+    if (n < 1 || n > sode::kPlainMaxN || m < 0 || m > sode::kPlainMaxN || d < 0)
+        return SODE_EINVAL;
+    sode_ctx* h = new (std::nothrow) sode_ctx;
+    if (!h)
+        return SODE_ENOMEM;
+    h->model = sode::kCustom;
+    h->n = n;
+    h->m = m;
+    h->d = d;
+    h->drift_src = drift_body;
+    h->diffusion_src = (m > 0 && diffusion_body) ? diffusion_body : "";
+    *out = h;
+    return SODE_OK;
+}
+
+int sode_build(sode_t h)
+{
+    if (!h)
+        return SODE_EINVAL;
+    if (h->model != sode::kCustom)
+        return SODE_OK;
+    return sode::rtc_build(h, h->precision);
+}
+
+int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed)
+{
+    if (!h)
+        return SODE_EINVAL;
+    if (needed)
+        *needed = h->build_log.size() + 1;
+    if (buf && len > 0) {
+        const size_t k = h->build_log.size() < len - 1 ? h->build_log.size() : len - 1;
+        std::memcpy(buf, h->build_log.data(), k);
+        buf[k] = '\0';
+    }
     return SODE_OK;
 }
 
@@ -323,6 +379,8 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
     r.out = out;
     r.stream = static_cast<hipStream_t>(stream);
 
+    if (kernel == 4)
+        return sode::rtc_launch(h, r, h->precision);
     hipError_t e;
     if (kernel == 3)
         e = sode::launch_rnn_mfma_f32(r, h->gemm);
@@ -495,6 +553,7 @@ int sode_destroy(sode_t h)
     if (h->scratch)
         (void)hipFree(h->scratch);
     sode::release_ragged(h);
+    sode::rtc_release(h);
     delete h;
     return SODE_OK;
 }
