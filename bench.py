@@ -299,7 +299,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--baseline-steps", type=int, default=1000,
                     help="Euler steps for the plain FP64 comparison run")
-    ap.add_argument("--cpu-orbits", type=int, default=4,
+    ap.add_argument("--cpu-orbits", type=int, default=16,
                     help="orbits of the oracle sample (full 2x10^4 steps each)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--accuracy-study", type=int, default=0, metavar="REALISATIONS",
