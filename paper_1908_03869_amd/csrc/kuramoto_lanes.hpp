@@ -83,17 +83,17 @@ __device__ __forceinline__ void couple_across(const float (&phi)[P], float (&acc
 {
     float other[P], back[P];
 #pragma unroll
-    for (int b = 0; b < P; ++b) {
+    for (int b = 0; b < P; ++b)
         other[b] = row_rotate<16 - K>(phi[b]);
-        back[b] = 0.0f;
-    }
+    // back[b] starts from its first term (0 + s is not an identity under
+    // IEEE signed zeros, so a zero start would cost an add per b).
 #pragma unroll
     for (int a = 0; a < P; ++a) {
 #pragma unroll
         for (int b = 0; b < P; ++b) {
             const float s = sin_rev(other[b] - phi[a]);
             acc[a] += s;
-            back[b] += s;
+            back[b] = a == 0 ? s : back[b] + s;
         }
     }
 #pragma unroll
@@ -113,17 +113,22 @@ __device__ __forceinline__ void couple_rotations(const float (&phi)[P], float (&
 template <int P>
 __device__ __forceinline__ void coupling_sums(const float (&phi)[P], float (&acc)[P])
 {
+    // Pairs inside the lane.  Each sum starts from its first term (with
+    // P = 1 there is none and the sums start at 0); the pair order and thus
+    // the rounding are those of a zero start.
+    if constexpr (P == 1) {
+        acc[0] = 0.0f;
+    } else {
 #pragma unroll
-    for (int a = 0; a < P; ++a)
-        acc[a] = 0.0f;
-    // Pairs inside the lane.
+        for (int a = 0; a < P; ++a) {
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-#pragma unroll
-        for (int b = a + 1; b < P; ++b) {
-            const float s = sin_rev(phi[b] - phi[a]);
-            acc[a] += s;
-            acc[b] -= s;
+            for (int b = a + 1; b < P; ++b) {
+                const float s = sin_rev(phi[b] - phi[a]);
+                // In this order every sum's first term comes from the pair
+                // (0, b): acc[0] from (0, 1), acc[b] from (0, b).
+                acc[a] = (a == 0 && b == 1) ? s : acc[a] + s;
+                acc[b] = a == 0 ? -s : acc[b] - s;
+            }
         }
     }
     couple_rotations<P, 1>(phi, acc);
