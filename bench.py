@@ -303,6 +303,8 @@ def parse():
     ap.add_argument("--cpu-orbits", type=int, default=16,
                     help="orbits of the oracle sample (full 2x10^4 steps each)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--grid-only", action="store_true",
+                    help="time only the n = 64 grid kernel (for short profiler runs)")
     ap.add_argument("--accuracy-study", type=int, default=0, metavar="REALISATIONS",
                     help="instead of the benchmark line, run the Sec. 2.3.1 accuracy study "
                          "with this many realisations per (K, dt), oracle alongside")
@@ -373,42 +375,46 @@ def main():
     achieved = work["slots"] * orbits * nsteps / (kernel_ms * 1e-3)
     r_gpu = out[:, -1, 0].double().cpu().numpy()
 
-    # Plain FP64 one-orbit-per-lane kernel on the same ensemble (fewer steps;
-    # its per-step cost does not depend on the step count).
-    it64 = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=64, observable="kuramoto_r")
-    X64, p64 = X0.double(), p.double()
-    bsteps = args.baseline_steps
-    out64 = torch.empty((orbits, bsteps // stride + 1, 1), dtype=torch.float64, device=dev)
-    it64.integrate(X64[:256], p64[:256], 0.0, w["dt"], stride, stride, w["seed"])
-    torch.cuda.synchronize()
-    b0 = torch.cuda.Event(enable_timing=True)
-    b1 = torch.cuda.Event(enable_timing=True)
-    b0.record(stream)
-    it64.integrate(X64, p64, 0.0, w["dt"], bsteps, stride, w["seed"], out=out64)
-    b1.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = b0.elapsed_time(b1)
-    plain_rate = orbits * bsteps / (plain_ms * 1e-3)
+    plain_rate = mf_ms = None
+    r_mf = None
+    adj = rag = rnn = None
+    if not args.grid_only:
+        # Plain FP64 one-orbit-per-lane kernel on the same ensemble (fewer steps;
+        # its per-step cost does not depend on the step count).
+        it64 = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=64, observable="kuramoto_r")
+        X64, p64 = X0.double(), p.double()
+        bsteps = args.baseline_steps
+        out64 = torch.empty((orbits, bsteps // stride + 1, 1), dtype=torch.float64, device=dev)
+        it64.integrate(X64[:256], p64[:256], 0.0, w["dt"], stride, stride, w["seed"])
+        torch.cuda.synchronize()
+        b0 = torch.cuda.Event(enable_timing=True)
+        b1 = torch.cuda.Event(enable_timing=True)
+        b0.record(stream)
+        it64.integrate(X64, p64, 0.0, w["dt"], bsteps, stride, w["seed"], out=out64)
+        b1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = b0.elapsed_time(b1)
+        plain_rate = orbits * bsteps / (plain_ms * 1e-3)
 
-    # The same ensemble with the O(n) mean-field form of the coupling.
-    itmf = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, observable="kuramoto_r",
-                           drift="meanfield")
-    outmf = torch.empty_like(out)
-    itmf.integrate(X0, p, 0.0, w["dt"], nsteps, stride, w["seed"], out=outmf)
-    torch.cuda.synchronize()
-    m0 = torch.cuda.Event(enable_timing=True)
-    m1 = torch.cuda.Event(enable_timing=True)
-    m0.record(stream)
-    itmf.integrate(X0, p, 0.0, w["dt"], nsteps, stride, w["seed"], out=outmf)
-    m1.record(stream)
-    torch.cuda.synchronize()
-    mf_ms = m0.elapsed_time(m1)
-    r_mf = outmf[:, -1, 0].double().cpu().numpy()
-    itmf.close()
+        # The same ensemble with the O(n) mean-field form of the coupling.
+        itmf = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, observable="kuramoto_r",
+                               drift="meanfield")
+        outmf = torch.empty_like(out)
+        itmf.integrate(X0, p, 0.0, w["dt"], nsteps, stride, w["seed"], out=outmf)
+        torch.cuda.synchronize()
+        m0 = torch.cuda.Event(enable_timing=True)
+        m1 = torch.cuda.Event(enable_timing=True)
+        m0.record(stream)
+        itmf.integrate(X0, p, 0.0, w["dt"], nsteps, stride, w["seed"], out=outmf)
+        m1.record(stream)
+        torch.cuda.synchronize()
+        mf_ms = m0.elapsed_time(m1)
+        r_mf = outmf[:, -1, 0].double().cpu().numpy()
+        itmf.close()
 
-    adj = adjoint_leg(sode, torch, workloads, dev)
-    rag = ragged_leg(sode, torch, workloads, dev)
-    rnn = rnn_leg(sode, torch, workloads, dev)
+        adj = adjoint_leg(sode, torch, workloads, dev)
+        rag = ragged_leg(sode, torch, workloads, dev)
+        rnn = rnn_leg(sode, torch, workloads, dev)
 
     cpu = None
     err = err_mf = None
@@ -428,7 +434,8 @@ def main():
                "sample": f"{len(rows)} grid-diagonal orbits x {nsteps} steps, FP64, "
                          f"single-threaded, {cpu_s:.1f} s"}
         err = float(np.max(np.abs(r_gpu[rows] - ref[:, -1, 0])))
-        err_mf = float(np.max(np.abs(r_mf[rows] - ref[:, -1, 0])))
+        if r_mf is not None:
+            err_mf = float(np.max(np.abs(r_mf[rows] - ref[:, -1, 0])))
 
     line = {
         "metric": "orbit*steps/s (Kuramoto n=64 FP32 Euler-Maruyama ensemble)",
@@ -454,11 +461,13 @@ def main():
                      "kernel_ms": kernel_ms,
                      "slots_per_orbit_step": work["slots"]},
         "cpu_baseline": cpu,
-        "plain_fp64": {"value": plain_rate, "unit": "orbit*steps/s", "nsteps": bsteps,
-                       "speedup_of_value": value / plain_rate},
+        "plain_fp64": None if plain_rate is None else {
+            "value": plain_rate, "unit": "orbit*steps/s", "nsteps": args.baseline_steps,
+            "speedup_of_value": value / plain_rate},
         "error": {"max_abs_dr_final": err, "tolerance": 1e-4},
-        "meanfield": {"value": orbits * nsteps / (mf_ms * 1e-3), "unit": "orbit*steps/s",
-                      "kernel_ms": mf_ms, "max_abs_dr_final": err_mf},
+        "meanfield": None if mf_ms is None else {
+            "value": orbits * nsteps / (mf_ms * 1e-3), "unit": "orbit*steps/s",
+            "kernel_ms": mf_ms, "max_abs_dr_final": err_mf},
         "adjoint": adj,
         "ragged": rag,
         "rnn": rnn,
