@@ -192,12 +192,12 @@ def paper_sweep(sode, torch, workloads, dev, reps: int) -> None:
     """The speed protocol of Sec. 2.2.1 (Tables S1-S3): Kuramoto N in
     {5, 10, 15}, M orbits from 512 to 163,840, K = 1, 8000 Euler-Maruyama
     steps of 0.05 s, in binary64 and binary32 on the one-orbit-per-lane
-    kernel and in binary32 on the 16-lane kernel (padded rows), with the
-    pairwise and the mean-field drift.  One JSON line per case: the kernel time with inputs
+    kernel and on the 16-lane kernels (padded rows), with the pairwise and
+    the mean-field drift.  One JSON line per case: the kernel time with inputs
     resident in HBM and the host-to-host time (upload of X0 and p, the
     integration, download of the saved states), each the median of `reps`
     runs after one warm-up."""
-    cases = [(64, "plain"), (32, "plain"), (32, "coupled")]
+    cases = [(64, "plain"), (64, "coupled"), (32, "plain"), (32, "coupled")]
     for prec, kernel in cases:
         dtype = torch.float64 if prec == 64 else torch.float32
         for N in PAPER_N:

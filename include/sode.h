@@ -157,14 +157,18 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  1 = Kuramoto order parameter r of Eq. (7), Sec. 2.3.1
  *                      (q = 1; Kuramoto only).
  *   "kernel"       0 = auto; 1 = plain (one orbit per lane, any model,
- *                  either precision); 2 = coupled (Kuramoto, precision 32,
- *                  method EM, n <= 128: 16 lanes per orbit exchange phases
+ *                  either precision); 2 = coupled (Kuramoto, method EM,
+ *                  n <= 128 in binary32, n <= 64 in binary64: 16 lanes per
+ *                  orbit exchange phases
  *                  through DPP row rotations; an n that is not a multiple
  *                  of 16 runs padded with oscillators frozen at phase 0
  *                  whose coupling is cancelled); 3 = matrix (see "gemm").
  *                  Auto takes coupled for binary32 Kuramoto EM with
- *                  8 <= n <= 128 (n < 8: only up to 65,536 orbits),
- *                  matrix for a supported dense network, else plain.
+ *                  8 <= n <= 128 (n < 8: only up to 65,536 orbits) and for
+ *                  binary64 Kuramoto EM with n <= 16 where it is faster
+ *                  (pairwise: n >= 12 or up to 40,960 orbits; mean-field:
+ *                  up to 16,384 orbits), matrix for a supported dense
+ *                  network, else plain.
  *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
  *                  used by every orbit.
  *   "gemm"         matrix kernel (model "rnn", precision 32, method EM,

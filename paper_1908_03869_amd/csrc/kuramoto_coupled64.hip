@@ -1,0 +1,291 @@
+// kuramoto_coupled64.hip - binary64 Euler-Maruyama integration of stochastic
+// Kuramoto networks (Eq. 5/6 of Sec. 2.2.1), 16 lanes per orbit.
+//
+// The binary64 counterpart of kuramoto_coupled.hip, for the precision the
+// paper measured in (Sec. 2.2.1): lane l of a 16-lane DPP row owns the
+// P = ceil(N/16) oscillators P*l .. P*l+P-1 (rows of N < 16P padded with
+// oscillators frozen at phase 0 whose terms are cancelled, as in the binary32
+// kernel); every unordered pair {i, j} is evaluated once with the correctly
+// rounded binary64 sine and used for both oscillators; 64-bit values cross
+// lanes as two 32-bit DPP row rotations.  The state is kept in radians and
+// wrapped to [-pi, pi] every step (theta - k 2pi_hi - k 2pi_lo, no rounding
+// when k = 0).  Normals are the binary64 Box-Muller pairs of the plain
+// kernel and the oracle.  Compared with one orbit per lane it moves 16x
+// more lanes through each step, which matters when the ensemble is too
+// small to fill the chip (Sec. 2.2.1 starts at 512 orbits).
+#include "launch.hpp"
+#include "noise.hpp"
+
+namespace sode {
+namespace {
+
+constexpr double kTwoPiHi = 6.283185307179586232;      // binary64 nearest to 2 pi
+constexpr double kTwoPiLo = 2.4492935982947064e-16;    // 2 pi - kTwoPiHi
+constexpr double kInvTwoPi = 0.15915494309189534561;
+constexpr double kPi = 3.1415926535897931160;          // binary64 nearest to pi
+
+// Value of `v` held by the lane R rotations away in the same 16-lane row.
+template <int R>
+__device__ __forceinline__ double row_rotate64(double v)
+{
+    static_assert(R >= 1 && R <= 15, "row rotation amount");
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x120 + R, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x120 + R, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ double row_sum64(double v)
+{
+    v += row_rotate64<8>(v);
+    v += row_rotate64<4>(v);
+    v += row_rotate64<2>(v);
+    v += row_rotate64<1>(v);
+    return v;
+}
+
+__device__ __forceinline__ double wrap64(double x)
+{
+    const double k = rint(x * kInvTwoPi);
+    x = fma(-k, kTwoPiHi, x);
+    return fma(-k, kTwoPiLo, x);
+}
+
+__device__ __forceinline__ double load_phase64(double x) { return fabs(x) <= kPi ? x : wrap64(x); }
+
+// Pairs between this lane and the lane K rotations away (K = 1..7): this
+// lane evaluates them and returns the negated partial sums with the inverse
+// rotation.
+template <int P, int K>
+__device__ __forceinline__ void couple_across64(const double (&th)[P], double (&acc)[P])
+{
+    double other[P], back[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b)
+        other[b] = row_rotate64<16 - K>(th[b]);
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+            const double s = sin(other[b] - th[a]);
+            acc[a] += s;
+            back[b] = a == 0 ? s : back[b] + s;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < P; ++b)
+        acc[b] -= row_rotate64<K>(back[b]);
+    if constexpr (K < 7)
+        couple_across64<P, K + 1>(th, acc);
+}
+
+// sum_j sin(theta_j - theta_i) for the lane's P oscillators (pads included).
+template <int P>
+__device__ __forceinline__ void coupling_sums64(const double (&th)[P], double (&acc)[P])
+{
+    if constexpr (P == 1) {
+        acc[0] = 0.0;
+    } else {
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+#pragma unroll
+            for (int b = a + 1; b < P; ++b) {
+                const double s = sin(th[b] - th[a]);
+                acc[a] = (a == 0 && b == 1) ? s : acc[a] + s;
+                acc[b] = a == 0 ? -s : acc[b] - s;
+            }
+        }
+    }
+    couple_across64<P, 1>(th, acc);
+    double other[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b)
+        other[b] = row_rotate64<8>(th[b]);
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+#pragma unroll
+        for (int b = 0; b < P; ++b)
+            acc[a] += sin(other[b] - th[a]);
+    }
+}
+
+// Binary64 normals P*l .. P*l+P-1 of one orbit at global step k: the Philox
+// blocks the lane's range touches, each giving four normals in the order of
+// the oracle (words 0,1 -> normals 4b, 4b+1; words 2,3 -> 4b+2, 4b+3).
+template <int P>
+__device__ __forceinline__ void lane_normals64(const Stream& st, uint32_t k, int l, double (&xi)[P])
+{
+    constexpr int NB = (P + 6) / 4;  // ceil((P + 3) / 4) blocks at most
+    const int j0 = P * l;
+    const int off = j0 & 3;
+    double z[4 * NB];
+#pragma unroll
+    for (int g = 0; g < NB; ++g) {
+        const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)((j0 >> 2) + g), 0u, st.key_lo, st.key_hi);
+        box_muller_f64(w.w0, w.w1, z[4 * g + 0], z[4 * g + 1]);
+        box_muller_f64(w.w2, w.w3, z[4 * g + 2], z[4 * g + 3]);
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        xi[i] = off == 0 ? z[i] : off == 1 ? z[i + 1] : off == 2 ? z[i + 2] : z[i + 3];
+}
+
+struct Coupled64Args {
+    const double* __restrict__ X0;
+    const double* __restrict__ p;
+    double* __restrict__ out;
+    const uint32_t* __restrict__ ids;
+    const uint64_t* __restrict__ seeds;
+    int n, p_per_orbit, observable;
+    int64_t orbits, stride, nsave;
+    double dt, sqdt;
+    uint64_t seed, orbit_offset, step_offset;
+};
+
+// r of Eq. (7) over the n real oscillators of the row.
+template <int P>
+__device__ __forceinline__ double order_parameter64(const double (&th)[P], const double (&w)[P], int n)
+{
+    double c = 0.0, s = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        c += cos(th[q]) * w[q];
+        s += sin(th[q]) * w[q];
+    }
+    const double C = row_sum64(c), S = row_sum64(s);
+    return sqrt(C * C + S * S) / (double)n;
+}
+
+template <int P, bool PAD, bool MF>
+__global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64Args a)
+{
+    const int l = threadIdx.x & 15;
+    const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    // Whole rows are in or out together, so no rotation reads a finished lane.
+    if (o >= a.orbits)
+        return;
+    const int n = PAD ? a.n : 16 * P;
+    const double* __restrict__ p = a.p + (a.p_per_orbit ? o * (int64_t)(2 * n + 1) : 0);
+    const int q = a.observable == kKuramotoR ? 1 : n;
+    double* __restrict__ out_row = a.out + o * a.nsave * q;
+
+    // Per oscillator: omega dt, p sqrt(dt), K dt / N, weight (0 for pads).
+    double th[P], drift0[P], noise[P], kc[P], w[P];
+    const double kcv = p[0] * (a.dt / (double)n);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int osc = P * l + i;
+        const bool real = !PAD || osc < n;
+        th[i] = real ? load_phase64(a.X0[o * n + osc]) : 0.0;
+        drift0[i] = real ? p[1 + osc] * a.dt : 0.0;
+        noise[i] = real ? p[1 + n + osc] * a.sqdt : 0.0;
+        kc[i] = real ? kcv : 0.0;
+        w[i] = real ? 1.0 : 0.0;
+    }
+    const double pads = (double)(16 * P - n);
+    const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
+
+    auto save = [&](int64_t s) {
+        if (a.observable == kKuramotoR) {
+            const double r = order_parameter64<P>(th, w, n);
+            if (l == 0)
+                out_row[s] = r;
+        } else {
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const int osc = P * l + i;
+                if (!PAD || osc < n)
+                    out_row[s * n + osc] = th[i];
+            }
+        }
+    };
+
+    save(0);
+    uint32_t k = (uint32_t)a.step_offset;
+    for (int64_t s = 1; s < a.nsave; ++s) {
+        for (int64_t kk = 0; kk < a.stride; ++kk, ++k) {
+            double acc[P], xi[P];
+            if constexpr (MF) {
+                // sum_j sin(theta_j - theta_i) = cos(theta_i) S - sin(theta_i) C.
+                double cs[P], sn[P], c = 0.0, sv = 0.0;
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    sincos(th[i], &sn[i], &cs[i]);
+                    c += cs[i] * w[i];
+                    sv += sn[i] * w[i];
+                }
+                const double C = row_sum64(c), S = row_sum64(sv);
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    acc[i] = cs[i] * S - sn[i] * C;
+            } else {
+                coupling_sums64<P>(th, acc);
+                if constexpr (PAD) {
+#pragma unroll
+                    for (int i = 0; i < P; ++i)
+                        acc[i] = fma(pads, sin(th[i]), acc[i]);
+                }
+            }
+            lane_normals64<P>(st, k, l, xi);
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                th[i] = wrap64(th[i] + (fma(kc[i], acc[i], drift0[i]) + noise[i] * xi[i]));
+        }
+        save(s);
+    }
+}
+
+template <int P, bool PAD>
+hipError_t launch_p64(const Request& r)
+{
+    Coupled64Args a;
+    a.X0 = static_cast<const double*>(r.X0);
+    a.p = static_cast<const double*>(r.p);
+    a.out = static_cast<double*>(r.out);
+    a.ids = r.orbit_ids;
+    a.seeds = r.orbit_seeds;
+    a.n = r.n;
+    a.p_per_orbit = r.p_per_orbit;
+    a.observable = r.observable;
+    a.orbits = r.orbits;
+    a.stride = r.stride;
+    a.nsave = r.nsave;
+    a.dt = r.dt;
+    a.sqdt = sqrt(r.dt);
+    a.seed = r.seed;
+    a.orbit_offset = r.orbit_offset;
+    a.step_offset = r.step_offset;
+    const int64_t threads = r.orbits * 16;
+    const dim3 block(256);
+    const dim3 grid((unsigned)((threads + 255) / 256));
+    if (r.drift == 1)
+        hipLaunchKernelGGL((kuramoto_coupled64_kernel<P, PAD, true>), grid, block, 0, r.stream, a);
+    else
+        hipLaunchKernelGGL((kuramoto_coupled64_kernel<P, PAD, false>), grid, block, 0, r.stream, a);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_padded_or_not64(const Request& r)
+{
+    if (r.n == 16 * P)
+        return launch_p64<P, false>(r);
+    return launch_p64<P, true>(r);
+}
+
+}  // namespace
+
+hipError_t launch_kuramoto_coupled_f64(const Request& r)
+{
+    switch ((r.n + 15) / 16) {
+    case 1: return launch_padded_or_not64<1>(r);
+    case 2: return launch_padded_or_not64<2>(r);
+    case 3: return launch_p64<3, true>(r);
+    case 4: return launch_padded_or_not64<4>(r);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool coupled64_supports(int n) { return n >= 1 && n <= 64; }
+
+}  // namespace sode

@@ -57,6 +57,9 @@ hipError_t launch_plain_implicit_f32(const Request& r);
 bool coupled_supports(int n);
 bool adjoint_supports(int n);
 hipError_t launch_kuramoto_coupled_f32(const Request& r);
+// The same mapping in binary64 (kuramoto_coupled64.hip), n <= 64.
+bool coupled64_supports(int n);
+hipError_t launch_kuramoto_coupled_f64(const Request& r);
 
 // Checkpointed forward pass and adjoint of the window-averaged order
 // parameter (Kuramoto, binary32, same sizes as the coupled kernel).

@@ -94,10 +94,13 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
 }
 
 // Which kernel a request goes to; SODE_EUNSUPPORTED if none can run it.
-// Auto: the 16-lane Kuramoto kernel wherever it applies, except for fewer
-// than 8 oscillators over many orbits, where a padded row wastes most of its
-// lanes and one orbit per lane fills the chip anyway (measured crossover:
-// between 40,960 and 81,920 orbits at n = 5).
+// Auto: in binary32 the 16-lane Kuramoto kernel wherever it applies, except
+// for fewer than 8 oscillators over many orbits, where a padded row wastes
+// most of its lanes and one orbit per lane fills the chip anyway (measured
+// crossover: between 40,960 and 81,920 orbits at n = 5).  In binary64 the
+// 16-lane kernel for n <= 16 where it measured faster on the paper's speed
+// protocol: pairwise from n = 12 at any size and below that up to 40,960
+// orbits, mean-field up to 16,384 orbits; otherwise one orbit per lane.
 int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 {
     if (h->model == sode::kCustom) {
@@ -109,8 +112,9 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
         *kernel = 4;
         return SODE_OK;
     }
-    const bool coupled_ok = h->model == sode::kKuramoto && h->precision == 32 &&
-                            h->method == sode::kEM && sode::coupled_supports(h->n);
+    const bool coupled_ok = h->model == sode::kKuramoto && h->method == sode::kEM &&
+                            (h->precision == 32 ? sode::coupled_supports(h->n)
+                                                : sode::coupled64_supports(h->n));
     const bool matrix_ok = h->model == sode::kRNN && h->precision == 32 && h->method == sode::kEM &&
                            h->shared_params && sode::rnn_mfma_supports(h->n);
     const bool implicit = h->method == sode::kImplicitEuler || h->method == sode::kImplicitMidpoint;
@@ -127,7 +131,10 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
         if (!plain_ok)
             return SODE_EUNSUPPORTED;
         *kernel = 1;
-    } else if (coupled_ok && (h->n >= 8 || orbits <= 65536)) {
+    } else if (coupled_ok && h->precision == 32 && (h->n >= 8 || orbits <= 65536)) {
+        *kernel = 2;
+    } else if (coupled_ok && h->precision == 64 && h->n <= 16 &&
+               (h->drift == 1 ? orbits <= 16384 : (h->n >= 12 || orbits <= 40960))) {
         *kernel = 2;
     } else if (matrix_ok) {
         *kernel = 3;
@@ -385,7 +392,7 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
     if (kernel == 3)
         e = sode::launch_rnn_mfma_f32(r, h->gemm);
     else if (kernel == 2)
-        e = sode::launch_kuramoto_coupled_f32(r);
+        e = h->precision == 64 ? sode::launch_kuramoto_coupled_f64(r) : sode::launch_kuramoto_coupled_f32(r);
     else if (h->precision == 64)
         e = sode::launch_plain_f64(r);
     else

@@ -122,10 +122,7 @@ def test_unsupported_kernel_requests():
     abi.sode_destroy(h)
     st, h = abi.sode_create("kuramoto", 64, 64, 129)
     abi.sode_set_option(h, "kernel", 2)
-    abi.sode_set_option(h, "precision", 64)  # coupled is binary32 only
-    assert _call(h) == abi.SODE_EUNSUPPORTED
-    abi.sode_set_option(h, "precision", 32)
-    abi.sode_set_option(h, "method", 1)  # and Euler-Maruyama only
+    abi.sode_set_option(h, "method", 1)  # coupled is Euler-Maruyama only
     assert _call(h) == abi.SODE_EUNSUPPORTED
     abi.sode_destroy(h)
     st, h = abi.sode_create("ou", 200, 200, 3)  # beyond the plain kernel's 128 states

@@ -25,7 +25,7 @@ def test_small_kuramoto_fp64_full_workload(gpu):
     10^4 steps, every orbit against the oracle: max |dtheta| <= 1e-10."""
     w = workloads.kuramoto_small()
     log("kuramoto_small fp64 plain, 1024 orbits x 1e4 steps")
-    got = run_library(w, precision=64)
+    got = run_library(w, precision=64, kernel="plain")
     want = run_oracle(w)
     assert got.shape == want.shape == (1024, 101, 4)
     err = circular_diff(got, want).max()
@@ -50,7 +50,7 @@ def test_plain_models_fp64(gpu, model, n, m, d, p, x0):
     w = dict(model=model, n=n, m=m, d=d, X0=X0, p=np.asarray(p, float), t0=0.0, dt=1e-2,
              nsteps=400, stride=40, seed=99)
     log(f"plain fp64 {model} n={n}")
-    got = run_library(w, precision=64)
+    got = run_library(w, precision=64, kernel="plain")
     want = run_oracle(w)
     scale = np.maximum(1.0, np.abs(want))
     assert np.max(np.abs(got - want) / scale) <= 1e-10
@@ -88,7 +88,7 @@ def test_noise_words_bit_exact_fp64(gpu):
     w = dict(model="ou", n=n, m=n, d=3, X0=np.zeros((orbits, n)), p=np.array([0.0, 0.0, 1.0]),
              t0=0.0, dt=1.0, nsteps=1, stride=1, seed=0xDEADBEEF12345)
     log("noise words fp64")
-    got = run_library(w, precision=64, step_offset=987654)[:, 1, :]
+    got = run_library(w, precision=64, kernel="plain", step_offset=987654)[:, 1, :]
 
     def uniforms(z):
         z0, z1 = z[..., 0::2], z[..., 1::2]
