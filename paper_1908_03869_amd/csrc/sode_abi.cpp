@@ -99,8 +99,9 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
 // most of its lanes and one orbit per lane fills the chip anyway (measured
 // crossover: between 40,960 and 81,920 orbits at n = 5).  In binary64 the
 // 16-lane kernel for n <= 16 where it measured faster on the paper's speed
-// protocol: pairwise from n = 12 at any size and below that up to 40,960
-// orbits, mean-field up to 16,384 orbits; otherwise one orbit per lane.
+// protocol: pairwise from n = 12 at any size and below that up to 400 n^2
+// orbits (one orbit per lane costs ~n^2 per orbit-step, the padded row a
+// constant), mean-field up to 16,384 orbits; otherwise one orbit per lane.
 int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 {
     if (h->model == sode::kCustom) {
@@ -134,7 +135,8 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
     } else if (coupled_ok && h->precision == 32 && (h->n >= 8 || orbits <= 65536)) {
         *kernel = 2;
     } else if (coupled_ok && h->precision == 64 && h->n <= 16 &&
-               (h->drift == 1 ? orbits <= 16384 : (h->n >= 12 || orbits <= 40960))) {
+               (h->drift == 1 ? orbits <= 16384
+                              : (h->n >= 12 || orbits <= 400 * (int64_t)h->n * h->n))) {
         *kernel = 2;
     } else if (matrix_ok) {
         *kernel = 3;
