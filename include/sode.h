@@ -325,7 +325,12 @@ int sode_ensemble_stats(sode_t h, const void* out, int64_t orbits, int64_t cols,
 
 /*
  * sode_sync - wait for the handle's last launch and report device errors.
- * Returns SODE_EDEVICE if the stream reported an error.
+ * Returns SODE_EDEVICE if the stream reported an error, else
+ * SODE_ENONFINITE if any value saved by sode_integrate(_ex) or
+ * sode_integrate_ragged since the previous sode_sync was NaN or infinite
+ * (the kernels raise a per-device flag of the handle; this call reads and
+ * clears it), else SODE_OK.  The flag (4 bytes per device) is allocated by
+ * the first integrate call on a device.
  */
 int sode_sync(sode_t h);
 

@@ -11,7 +11,7 @@ from . import abi
 from .abi import SodeError, check
 
 __all__ = ["abi", "Integrator", "SodeError", "check", "OPTION_VALUES", "KuramotoWindowR",
-           "RaggedBatch"]
+           "KuramotoTimeAvgR", "RaggedBatch", "integrate", "noises"]
 
 OPTION_VALUES = {
     "method": {"em": 0, "rk4": 1, "milstein": 2, "implicit_euler": 3, "implicit_midpoint": 4},
@@ -293,3 +293,34 @@ class _Lazy:
 
 
 KuramotoWindowR = _Lazy()
+# The name the design blueprint uses for the same function.
+KuramotoTimeAvgR = KuramotoWindowR
+
+
+def noises(model: str, n: int) -> int:
+    """m, the number of Wiener processes of a built-in model of n equations."""
+    return n // 2 if model == "fhn" else n
+
+
+def integrate(model: str, X0, p, t0: float, dt: float, nsteps: int, stride: int, seed: int,
+              **options):
+    """One-call form of Integrator(...).integrate(...): n from X0[orbits, n],
+    d from p ([d] shared by all orbits, or [orbits, d]), precision from the
+    tensors' dtype; other options (method, observable, kernel, drift, ...) as
+    keywords.  The output is allocated with torch and the work is queued on
+    the current stream; the temporary handle is released on return, which
+    waits for the work to finish and raises on a device error or a
+    non-finite saved value."""
+    import torch
+    n = int(X0.shape[1])
+    d = int(p.shape[-1])
+    prec = 64 if X0.dtype == torch.float64 else 32
+    options.setdefault("precision", prec)
+    options.setdefault("shared_params", int(p.dim() == 1))
+    it = Integrator(model, n, noises(model, n), d, **options)
+    try:
+        out = it.integrate(X0, p, t0, dt, nsteps, stride, seed)
+        it.sync()
+    finally:
+        it.close()
+    return out

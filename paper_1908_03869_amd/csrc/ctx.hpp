@@ -55,6 +55,10 @@ struct sode_ctx {
     uint64_t rg_graph_key = 0;
     hipStream_t rg_capture = nullptr;
 
+    // Per device: a flag the kernels raise when a saved value is NaN or
+    // infinite; read and cleared by sode_sync.
+    std::map<int, int*> nonfinite;
+
     // Model given as source text (model == kCustom): the two function
     // bodies, the compiled code objects and loaded modules, the last log.
     std::string drift_src, diffusion_src, build_log;
@@ -63,6 +67,9 @@ struct sode_ctx {
 
 namespace sode {
 void release_ragged(sode_ctx* h);
+// The non-finite flag of the current device (allocated and cleared on first
+// use); null if that fails.
+int* nonfinite_flag(sode_ctx* h);
 // Compile the handle's source-text model for a precision (no device needed).
 int rtc_build(sode_ctx* h, int precision);
 // Compile if needed, load on the current device and launch.

@@ -30,6 +30,7 @@
 // the batch is balanced without knowing in advance which instance finishes
 // when.  The same group body also runs non-persistently (one block per
 // group), which gives bitwise the same result.
+#include "devmath.hpp"
 #include "launch.hpp"
 #include "noise.hpp"
 
@@ -92,6 +93,8 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
         for (int u = 0; u < U; ++u) {
             const int j = U * l + u;
             if (j < N) {
+                note_nonfinite(a.nonfinite, v[u]);
+                note_nonfinite(a.nonfinite, w[u]);
                 row[j] = v[u];
                 row[N + j] = w[u];
             }

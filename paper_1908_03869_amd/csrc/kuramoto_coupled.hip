@@ -4,6 +4,7 @@
 // the padding of sizes that are not multiples of 16 are described in
 // kuramoto_lanes.hpp), pairwise or through the mean-field identity.  Saves
 // the state or the order parameter every `stride` steps (Sec. 2.1.4).
+#include "devmath.hpp"
 #include "kuramoto_lanes.hpp"
 #include "launch.hpp"
 
@@ -22,6 +23,7 @@ struct CoupledArgs {
     int64_t orbits, stride, nsave;
     float dt, sqdt, dt_over_n, inv_n;
     uint64_t seed, orbit_offset, step_offset;
+    int* nonfinite;
 };
 
 // Observable of the row at save s: the state (the lane's real oscillators)
@@ -36,14 +38,18 @@ __device__ __forceinline__ void save(const CoupledArgs& a, int l, const float (&
             r = order_parameter_padded<P>(th, c.weight, a.inv_n);
         else
             r = order_parameter<P>(th);
-        if (l == 0)
+        if (l == 0) {
+            note_nonfinite(a.nonfinite, r);
             out_row[s] = r;
+        }
     } else {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             const int osc = P * l + q;
-            if (!PAD || osc < a.n)
+            if (!PAD || osc < a.n) {
+                note_nonfinite(a.nonfinite, th[q]);
                 out_row[s * a.n + osc] = th[q];
+            }
         }
     }
 }
@@ -105,6 +111,7 @@ hipError_t launch_p(const Request& r)
     a.seed = r.seed;
     a.orbit_offset = r.orbit_offset;
     a.step_offset = r.step_offset;
+    a.nonfinite = r.nonfinite;
     const int64_t threads = r.orbits * 16;
     const dim3 block(256);
     const dim3 grid((unsigned)((threads + 255) / 256));

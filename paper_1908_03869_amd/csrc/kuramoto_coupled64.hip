@@ -13,6 +13,7 @@
 // kernel and the oracle.  Compared with one orbit per lane it moves 16x
 // more lanes through each step, which matters when the ensemble is too
 // small to fill the chip (Sec. 2.2.1 starts at 512 orbits).
+#include "devmath.hpp"
 #include "launch.hpp"
 #include "noise.hpp"
 
@@ -140,6 +141,7 @@ struct Coupled64Args {
     int64_t orbits, stride, nsave;
     double dt, sqdt;
     uint64_t seed, orbit_offset, step_offset;
+    int* nonfinite;
 };
 
 // r of Eq. (7) over the n real oscillators of the row.
@@ -188,14 +190,18 @@ __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64
     auto save = [&](int64_t s) {
         if (a.observable == kKuramotoR) {
             const double r = order_parameter64<P>(th, w, n);
-            if (l == 0)
+            if (l == 0) {
+                note_nonfinite(a.nonfinite, r);
                 out_row[s] = r;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 const int osc = P * l + i;
-                if (!PAD || osc < n)
+                if (!PAD || osc < n) {
+                    note_nonfinite(a.nonfinite, th[i]);
                     out_row[s * n + osc] = th[i];
+                }
             }
         }
     };
@@ -255,6 +261,7 @@ hipError_t launch_p64(const Request& r)
     a.seed = r.seed;
     a.orbit_offset = r.orbit_offset;
     a.step_offset = r.step_offset;
+    a.nonfinite = r.nonfinite;
     const int64_t threads = r.orbits * 16;
     const dim3 block(256);
     const dim3 grid((unsigned)((threads + 255) / 256));

@@ -29,6 +29,7 @@ struct Request {
     int compensated;  // binary32 coupled kernels: two-sum compensated state
     int drift;        // Kuramoto coupling sum: 0 pairwise, 1 mean-field identity
     void* out;  // [orbits][nsave][q]
+    int* nonfinite;  // device flag raised by a NaN or infinite save (may be null)
     hipStream_t stream;
 };
 
@@ -120,6 +121,7 @@ struct RaggedKernelArgs {
     float* out;
     float dt, sqdt;
     int compensated;  // two-sum state (v and w carried as hi + lo)
+    int* nonfinite;   // device flag raised by a NaN or infinite save (may be null)
 };
 int ragged_shape_code(int lanes, int units);
 hipError_t launch_fhn_ragged(const RaggedKernelArgs& a, int persistent, int waves, hipStream_t stream);

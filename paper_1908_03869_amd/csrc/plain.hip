@@ -42,6 +42,7 @@ PlainArgs<R> plain_args(const Request& r)
     a.seed = r.seed;
     a.orbit_offset = r.orbit_offset;
     a.step_offset = r.step_offset;
+    a.nonfinite = r.nonfinite;
     return a;
 }
 template PlainArgs<double> plain_args<double>(const Request&);

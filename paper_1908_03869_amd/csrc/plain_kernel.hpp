@@ -25,6 +25,7 @@ struct PlainArgs {
     int64_t orbits, stride, nsave;
     R t0, dt, sqdt;
     uint64_t seed, orbit_offset, step_offset;
+    int* nonfinite;  // raised when a saved value is NaN or infinite (may be null)
 };
 
 template <typename R>
@@ -42,10 +43,14 @@ template <typename R>
 __device__ __forceinline__ void plain_save(const PlainArgs<R>& a, int n, const R* y, R* dst)
 {
     if (a.observable == kKuramotoR) {
-        dst[0] = plain_order_parameter(n, y);
+        const R r = plain_order_parameter(n, y);
+        note_nonfinite(a.nonfinite, r);
+        dst[0] = r;
     } else {
-        for (int i = 0; i < n; ++i)
+        for (int i = 0; i < n; ++i) {
+            note_nonfinite(a.nonfinite, y[i]);
             dst[i] = y[i];
+        }
     }
 }
 

@@ -217,6 +217,9 @@ RaggedKernelArgs kernel_args(const sode_ctx* h, const void* X0, const void* p, v
     a.dt = (float)dt;
     a.sqdt = (float)std::sqrt(dt);
     a.compensated = h->compensated;
+    int dev = 0;
+    const auto it = hipGetDevice(&dev) == hipSuccess ? h->nonfinite.find(dev) : h->nonfinite.end();
+    a.nonfinite = it == h->nonfinite.end() ? nullptr : it->second;
     return a;
 }
 
@@ -328,6 +331,8 @@ extern "C" int sode_integrate_ragged(sode_t h, const sode_instance_t* inst, int3
     if (v != SODE_OK)
         return v;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!nonfinite_flag(h))
+        return SODE_ENOMEM;
 
     // Lane shape and grid: fixed options, else the tuned pair for this batch
     // shape (autotuning on first sight).
@@ -371,6 +376,7 @@ extern "C" int sode_integrate_ragged(sode_t h, const sode_instance_t* inst, int3
         key = mix(key, dt);
         key = mix(key, grid);
         key = mix(key, h->compensated);
+        key = mix(key, a.nonfinite);
         if (!h->rg_exec || key != h->rg_graph_key) {
             if (h->launched && hipStreamSynchronize(h->last_stream) != hipSuccess)
                 return SODE_EDEVICE;

@@ -27,6 +27,7 @@
 //          hi.hi + hi.lo + lo.hi (Henry, Tang & Heinecke, ARITH 2019),
 //          ~2^-16 relative error;
 //   FP32   binary32 operands (v_mfma_f32_32x32x2f32).
+#include "devmath.hpp"
 #include "launch.hpp"
 #include "noise.hpp"
 
@@ -52,6 +53,7 @@ struct RnnArgs {
     int64_t orbits, stride, nsave;
     float dt, sqdt;
     uint64_t seed, orbit_offset, step_offset;
+    int* nonfinite;
 };
 
 // tanh(x) = 1 - 2 / (exp(2x) + 1) on the transcendental unit; exact limits
@@ -136,8 +138,10 @@ __global__ __launch_bounds__(64 * (N / 32)) void rnn_mfma_kernel(const RnnArgs a
     auto save = [&](int64_t s) {
         if (valid) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
+            for (int r = 0; r < 16; ++r) {
+                note_nonfinite(a.nonfinite, X[r]);
                 out_row[s * N + row[r]] = X[r];
+            }
         }
     };
     // tanh of the lane's elements into LDS buffer `buf`.
@@ -246,6 +250,7 @@ hipError_t launch_n(const Request& r)
     a.seed = r.seed;
     a.orbit_offset = r.orbit_offset;
     a.step_offset = r.step_offset;
+    a.nonfinite = r.nonfinite;
     const size_t lds = Lds<N, MODE>::kBytes;
     auto kern = rnn_mfma_kernel<N, MODE>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -150,6 +150,27 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 
 }  // namespace
 
+namespace sode {
+int* nonfinite_flag(sode_ctx* h)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return nullptr;
+    const auto it = h->nonfinite.find(dev);
+    if (it != h->nonfinite.end())
+        return it->second;
+    int* f = nullptr;
+    if (hipMalloc(&f, sizeof(int)) != hipSuccess)
+        return nullptr;
+    if (hipMemset(f, 0, sizeof(int)) != hipSuccess) {
+        (void)hipFree(f);
+        return nullptr;
+    }
+    h->nonfinite[dev] = f;
+    return f;
+}
+}  // namespace sode
+
 extern "C" {
 
 int sode_version(void) { return kVersion; }
@@ -387,6 +408,9 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
     r.drift = h->drift;
     r.out = out;
     r.stream = static_cast<hipStream_t>(stream);
+    r.nonfinite = sode::nonfinite_flag(h);
+    if (!r.nonfinite)
+        return SODE_ENOMEM;
 
     if (kernel == 4)
         return sode::rtc_launch(h, r, h->precision);
@@ -422,7 +446,20 @@ int sode_sync(sode_t h)
     const hipError_t e = hipStreamSynchronize(h->last_stream);
     if (e != hipSuccess)
         return SODE_EDEVICE;
-    return status_of(h->last_error);
+    const int st = status_of(h->last_error);
+    if (st != SODE_OK)
+        return st;
+    for (auto& kv : h->nonfinite) {
+        int v = 0;
+        if (hipMemcpy(&v, kv.second, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            return SODE_EDEVICE;
+        if (v) {
+            if (hipMemset(kv.second, 0, sizeof(int)) != hipSuccess)
+                return SODE_EDEVICE;
+            return SODE_ENONFINITE;
+        }
+    }
+    return SODE_OK;
 }
 
 int sode_forward_ckpt(sode_t h, const void* X0, const void* p, int64_t orbits, double t0,
@@ -563,6 +600,8 @@ int sode_destroy(sode_t h)
         (void)hipFree(h->scratch);
     sode::release_ragged(h);
     sode::rtc_release(h);
+    for (auto& kv : h->nonfinite)
+        (void)hipFree(kv.second);
     delete h;
     return SODE_OK;
 }

@@ -110,10 +110,19 @@ def test_implicit_step_without_a_root_gives_nan(gpu):
     dt Y^2 - Y + X + dt = 0 has no real root, Newton cannot converge and the
     state becomes NaN (the oracle does the same); the other orbit, x = 0,
     has a root and stays finite."""
+    import torch
+    import paper_1908_03869_amd as sode
     X0 = np.array([[100.0], [0.0]])
     log("implicit step without a root")
-    got = _run("f[0] = y[0] * y[0] + 1;", None, 1, 0, 1, X0, np.array([0.0]), 0.0, 0.1, 1, 1, 1,
-               method="implicit_euler")
+    it = sode.Integrator.custom("f[0] = y[0] * y[0] + 1;", None, 1, 0, 1, precision=64,
+                                method="implicit_euler", shared_params=1)
+    out = it.integrate(torch.tensor(X0, device="cuda"), torch.zeros(1, dtype=torch.float64,
+                       device="cuda"), 0.0, 0.1, 1, 1, 1)
+    with pytest.raises(sode.SodeError) as e:  # the NaN is reported at the sync
+        it.sync()
+    assert e.value.status == sode.abi.SODE_ENONFINITE
+    got = out.cpu().numpy()
+    it.close()
     want = _oracle("f[0] = y[0] * y[0] + 1;", None, 1, 0, 1, X0, np.array([0.0]), 0.0, 0.1, 1,
                    1, 1, method="implicit_euler")
     assert np.isnan(want[0, 1, 0]) and np.isnan(got[0, 1, 0])

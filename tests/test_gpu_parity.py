@@ -229,3 +229,17 @@ def test_shared_params_equal_per_orbit_rows(gpu):
     rows = np.broadcast_to(w["p"], (50, w["d"])).copy()
     per = run_library(w, precision=32, p=rows, shared=False)
     np.testing.assert_array_equal(shared, per)
+
+
+def test_module_level_integrate_equals_handle(gpu):
+    """paper_1908_03869_amd.integrate(model, X0, p, ...) is the handle path."""
+    import torch
+    import paper_1908_03869_amd as sode
+    w = _grid(3, 5, 32, 300)
+    log("module-level integrate")
+    X0 = torch.tensor(w["X0"], dtype=torch.float32, device="cuda")
+    p = torch.tensor(w["p"], dtype=torch.float32, device="cuda")
+    a = sode.integrate("kuramoto", X0, p, 0.0, w["dt"], 300, 100, w["seed"],
+                       observable="kuramoto_r").cpu().numpy()
+    b = run_library(dict(w, nsteps=300, stride=100), precision=32)
+    np.testing.assert_array_equal(a, b.astype(np.float32))
