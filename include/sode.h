@@ -271,7 +271,8 @@ int sode_forward_ckpt(sode_t h, const void* X0, const void* p, int64_t orbits, d
  *   grad_p           [d] double, sum over orbits in a fixed order (may be
  *                    NULL if grad_p_per_orbit is given).
  *   grad_p_per_orbit [orbits][d] double, dL_dR[o] * dR_o/dp, or NULL.
- * The library keeps a device scratch area of orbits * ckpt_every * n floats
+ * The library keeps a device scratch area of orbits * ckpt_every * 2n floats
+ * (the recomputed states of a segment and the normals of each step)
  * (plus orbits * d doubles when grad_p_per_orbit is NULL) in the handle;
  * growing it may allocate (SODE_ENOMEM on failure).
  */

@@ -23,7 +23,8 @@
 // Memory: the forward pass stores every `every`-th state (checkpoints); the
 // reverse pass walks the segments last to first, recomputes a segment's
 // states from its checkpoint with the same em_step() as the forward pass,
-// parks them in a per-lane scratch area in HBM, and sweeps them backwards.
+// parks them with the normals of each step in a per-lane scratch area in
+// HBM, and sweeps them backwards.
 // Without compensation the recomputed states are bitwise those of the
 // forward pass; with it, a segment restarts from the checkpoint's leading
 // part (the trailing part, below 1e-7 rad, is dropped), which moves the
@@ -140,9 +141,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjointArgs a)
     const LaneCoefficients<P> c = lane_coefficients<P>(p, l, a.dt, a.sqdt, a.dt_over_n);
     const Stream st = orbit_stream(o, a.seed, a.orbit_offset, nullptr, nullptr);
     const float* __restrict__ ck = a.ckpt + o * a.nckpt * N + P * l;
-    // Scratch layout [orbit][step in segment][lane][P]: a row's 16 lanes
-    // write and read 16 * P consecutive floats per step.
-    float* __restrict__ seg = a.seg + (o * a.every * 16 + l) * P;
+    // Scratch layout [orbit][step in segment][lane][2P]: a lane's P phases
+    // X^k followed by the P normals of step k, so the reverse sweep does not
+    // draw the normals again; a row's 16 lanes write and read 32 P
+    // consecutive floats per step.
+    float* __restrict__ seg = a.seg + (o * a.every * 16 + l) * (2 * P);
     const int64_t nsteps = (a.nckpt - 1) * a.every;
 
     float lam[P];
@@ -172,20 +175,41 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjointArgs a)
             tl[i] = 0.0f;
         }
         for (int64_t j = 0; j < a.every; ++j) {
+            float* __restrict__ rec = seg + j * 16 * (2 * P);
 #pragma unroll
             for (int i = 0; i < P; ++i)
-                seg[j * 16 * P + i] = th[i];
+                rec[i] = th[i];
             if (j + 1 < a.every)
-                em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)(kbase + j)), l);
+                em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)(kbase + j)), l,
+                                     rec + P);
         }
-        // Reverse sweep over the segment.
+        // Reverse sweep over the segment.  The record of step j - 1 is
+        // loaded while step j is processed, off the dependency chain.
+        float nX[P], nxi[P];
+        {
+            const float* __restrict__ rec = seg + (a.every - 1) * 16 * (2 * P);
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                nX[i] = rec[i];
+            // The segment's last step was not taken by the recompute.
+            lane_normals<P>(st, (uint32_t)(a.step_offset + (uint64_t)(kbase + a.every - 1)), l, nxi);
+        }
         for (int64_t j = a.every - 1; j >= 0; --j) {
             const int64_t k = kbase + j;
             float X[P], xi[P], cs[P], sn[P], C, S;
 #pragma unroll
-            for (int i = 0; i < P; ++i)
-                X[i] = seg[j * 16 * P + i];
-            lane_normals<P>(st, (uint32_t)(a.step_offset + (uint64_t)k), l, xi);
+            for (int i = 0; i < P; ++i) {
+                X[i] = nX[i];
+                xi[i] = nxi[i];
+            }
+            if (j > 0) {
+                const float* __restrict__ rec = seg + (j - 1) * 16 * (2 * P);
+#pragma unroll
+                for (int i = 0; i < P; ++i) {
+                    nX[i] = rec[i];
+                    nxi[i] = rec[P + i];
+                }
+            }
             phase_sums<P>(X, cs, sn, C, S);
             float la = 0.0f, lb = 0.0f, kpart = 0.0f;
 #pragma unroll

@@ -228,9 +228,10 @@ __device__ __forceinline__ void mean_field_sums(const float (&phi)[P], float (&a
 // increment and the old trailing part are added with an error-free two-sum,
 // and a wrap moves the tail of 2 pi into tl.  MF: coupling through the
 // mean-field identity instead of pairwise sines.  PAD: see the top of the file.
+// xi_out (optional) receives the step's P normals.
 template <int P, bool COMP, bool MF = false, bool PAD = false>
 __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const LaneCoefficients<P, PAD>& c,
-                                        const Stream& st, uint32_t k, int l)
+                                        const Stream& st, uint32_t k, int l, float* xi_out = nullptr)
 {
     float phi[P], acc[P], xi[P];
 #pragma unroll
@@ -247,6 +248,11 @@ __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const La
         }
     }
     lane_normals<P>(st, k, l, xi);
+    if (xi_out) {  // the step's normals, for a caller that needs them again
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            xi_out[i] = xi[i];
+    }
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const float kc = PAD ? c.kc[i] : c.kc[0];

@@ -517,7 +517,8 @@ int sode_adjoint(sode_t h, const void* p, int64_t orbits, double t0, double dt, 
     if (orbits > 0 && (!p || !ckpt))
         return SODE_EINVAL;
     const size_t d = 2 * (size_t)h->n + 1;
-    const size_t seg_bytes = (size_t)orbits * (size_t)ckpt_every * (size_t)h->n * sizeof(float);
+    // Segment states and normals: [orbits][ckpt_every][2 n] floats.
+    const size_t seg_bytes = (size_t)orbits * (size_t)ckpt_every * (size_t)h->n * 2 * sizeof(float);
     const size_t rows_bytes = grad_p_per_orbit ? 0 : (size_t)orbits * d * sizeof(double);
     const size_t rows_offset = (seg_bytes + 255) / 256 * 256;
     const int sc = ensure_scratch(h, rows_offset + rows_bytes + 256);
