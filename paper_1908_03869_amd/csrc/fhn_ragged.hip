@@ -10,7 +10,7 @@
 // cross-lane data is the diffusive coupling of the two units at a lane's
 // edges: the left neighbour comes from lane l-1, the right one from lane
 // l+1 -- by DPP row_shr:1 / row_shl:1 when an instance fits in a 16-lane
-// row, by ds_bpermute (__shfl_up/__shfl_down) when it spans rows.  Reads
+// row, by DPP wave_shr:1 / wave_shl:1 when it spans rows.  Reads
 // that cross an instance boundary are never used: they only reach units 0
 // and N-1, whose missing neighbour is replaced by the unit itself (no-flux
 // ends).  Units with index >= N in the last lanes are computed and never
@@ -50,6 +50,10 @@ __device__ __forceinline__ float dpp_read(float v)
 // row_shr:1 -> value of lane l-1; row_shl:1 -> value of lane l+1 (same row).
 __device__ __forceinline__ float from_lower_lane(float v) { return dpp_read<0x111>(v); }
 __device__ __forceinline__ float from_upper_lane(float v) { return dpp_read<0x101>(v); }
+// wave_shr:1 / wave_shl:1: the same across the whole 64-lane wave (a GFX9
+// DPP form), one VALU operation instead of an LDS permute round trip.
+__device__ __forceinline__ float from_lower_lane_wave(float v) { return dpp_read<0x138>(v); }
+__device__ __forceinline__ float from_upper_lane_wave(float v) { return dpp_read<0x130>(v); }
 
 // x_hi + x_lo += inc without losing the rounding error of the sum.
 __device__ __forceinline__ void two_sum_add(float& hi, float& lo, float inc)
@@ -120,8 +124,8 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
             left_edge = from_lower_lane(v[U - 1]);
             right_edge = from_upper_lane(v[0]);
         } else {
-            left_edge = __shfl_up(v[U - 1], 1, 64);
-            right_edge = __shfl_down(v[0], 1, 64);
+            left_edge = from_lower_lane_wave(v[U - 1]);
+            right_edge = from_upper_lane_wave(v[0]);
         }
         float dv[U], dw[U];
 #pragma unroll
