@@ -43,7 +43,7 @@ SLOTS = {"valu": 1.0, "trans": 4.0, "imul": 2.0}
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a 1 GiB copy shows), for
 # the kernel as built from the current sources.  The algorithmic figure is
 # 103.3 MB (X0 and p read once, r written once).
-COUPLED_N64_HBM_BYTES = 50.97e6 + 53.00e6
+COUPLED_N64_HBM_BYTES = 50.98e6 + 52.91e6
 
 
 def algorithmic_slots_per_orbit_step(n: int, compensated: bool = True) -> dict:
@@ -156,7 +156,7 @@ def ragged_leg(sode, torch, workloads, dev, reps: int = 5) -> dict:
             "makespan_over_longest": ms / alone}
 
 
-def rnn_leg(sode, torch, workloads, dev) -> dict:
+def rnn_leg(sode, torch, workloads, dev, gemms=("bf16", "bf16x3", "fp32")) -> dict:
     """The n = 256 dense-network workload (8192 orbits, 5000 steps) with each
     matrix-product variant; MFMA work = 2 n^2 flops per orbit-step."""
     w = workloads.rnn_dense()
@@ -166,7 +166,8 @@ def rnn_leg(sode, torch, workloads, dev) -> dict:
     orbits = X0.shape[0]
     stream = torch.cuda.current_stream()
     res = {"workload": "rnn_dense_n256", "orbits": orbits, "nsteps": w["nsteps"]}
-    for gemm, products in (("bf16", 1), ("bf16x3", 3), ("fp32", 1)):
+    for gemm in gemms:
+        products = 3 if gemm == "bf16x3" else 1
         it = sode.Integrator("rnn", n, n, w["d"], precision=32, shared_params=1,
                              kernel="matrix", gemm=gemm)
         out = it.integrate(X0, p, 0.0, w["dt"], w["nsteps"], w["stride"], w["seed"])
@@ -308,6 +309,9 @@ def parse():
                     help="instead of the benchmark line, run the Sec. 2.3.1 accuracy study "
                          "with this many realisations per (K, dt), oracle alongside")
     ap.add_argument("--oracle-threads", type=int, default=16)
+    ap.add_argument("--rnn-only", choices=("bf16", "bf16x3", "fp32"), default=None,
+                    help="time only the dense-network workload with this matrix variant "
+                         "(one warm-up and one timed launch) and print its JSON")
     ap.add_argument("--paper-sweep", type=int, default=0, metavar="REPS",
                     help="instead of the benchmark line, time the Sec. 2.2.1 speed protocol "
                          "(N x M x precision x drift form), REPS runs per case")
@@ -335,6 +339,9 @@ def main():
         return
     if args.accuracy_study:
         accuracy_study(sode, torch, workloads, dev, args.accuracy_study, args.oracle_threads)
+        return
+    if args.rnn_only:
+        print(json.dumps(rnn_leg(sode, torch, workloads, dev, gemms=(args.rnn_only,))))
         return
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)

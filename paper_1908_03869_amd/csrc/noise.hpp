@@ -31,14 +31,18 @@ __device__ __forceinline__ Block4 philox_4x32_10(uint32_t c0, uint32_t c1, uint3
     constexpr uint32_t kMulEven2 = 0xCD9E8D57u;
     constexpr uint32_t kWeylLo = 0x9E3779B9u;
     constexpr uint32_t kWeylHi = 0xBB67AE85u;
+    // Bit i of the table is the result for input bits (a, b, c) = (i>>2, i>>1, i) & 1.
+    constexpr uint32_t kXor3 = 0x96u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        // One 32x32 -> 64-bit product per even word (a single v_mad_u64_u32).
+        // One 32x32 -> 64-bit product per even word (a single v_mad_u64_u32),
+        // and one three-input bitwise operation (v_bitop3_b32 with the truth
+        // table of a ^ b ^ c) per mixed word.
         const uint64_t p0 = (uint64_t)kMulEven0 * c0;
         const uint64_t p2 = (uint64_t)kMulEven2 * c2;
-        c0 = (uint32_t)(p2 >> 32) ^ c1 ^ key_lo;
+        c0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p2 >> 32), c1, key_lo, kXor3);
         c1 = (uint32_t)p2;
-        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ key_hi;
+        c2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, key_hi, kXor3);
         c3 = (uint32_t)p0;
         key_lo += kWeylLo;
         key_hi += kWeylHi;

@@ -62,7 +62,24 @@ struct RnnArgs {
 __device__ __forceinline__ float fast_tanh(float x)
 {
     const float e = __builtin_amdgcn_exp2f(x * kTwoLog2e);
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+    return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);  // 2 r is exact
+}
+
+// (hi, lo) bfloat16 pairs of two values: hi = bf16(y), lo = bf16(y - hi),
+// with one packed conversion per pair and the widening of hi done on bits.
+struct SplitPair {
+    uint32_t hi, lo;  // element 0 in bits 15:0, element 1 in bits 31:16
+};
+__device__ __forceinline__ SplitPair split_bf16(float y0, float y1)
+{
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 h = __builtin_convertvector(f32x2{y0, y1}, bf16x2);
+    const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+    const float r0 = y0 - __builtin_bit_cast(float, hb << 16);
+    const float r1 = y1 - __builtin_bit_cast(float, hb & 0xFFFF0000u);
+    const bf16x2 l = __builtin_convertvector(f32x2{r0, r1}, bf16x2);
+    return SplitPair{hb, __builtin_bit_cast(uint32_t, l)};
 }
 
 template <int N, int MODE>
@@ -157,17 +174,22 @@ __global__ __launch_bounds__(64 * (N / 32)) void rnn_mfma_kernel(const RnnArgs a
             __bf16* base = reinterpret_cast<__bf16*>(smem) + (size_t)buf * L::kParts * kOrbitsPerBlock * L::kPitchBf;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                bf16x4 hi, lo;
+                float y[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float y = fast_tanh(X[4 * g + e]);
-                    hi[e] = (__bf16)y;
-                    if constexpr (MODE == kRnnBf16x3)
-                        lo[e] = (__bf16)(y - (float)hi[e]);
+                for (int e = 0; e < 4; ++e)
+                    y[e] = fast_tanh(X[4 * g + e]);
+                if constexpr (MODE == kRnnBf16x3) {
+                    const SplitPair a01 = split_bf16(y[0], y[1]);
+                    const SplitPair a23 = split_bf16(y[2], y[3]);
+                    *reinterpret_cast<uint2*>(base + ol * L::kPitchBf + row[4 * g]) = uint2{a01.hi, a23.hi};
+                    *reinterpret_cast<uint2*>(base + (kOrbitsPerBlock + ol) * L::kPitchBf + row[4 * g]) = uint2{a01.lo, a23.lo};
+                } else {
+                    bf16x4 hi;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        hi[e] = (__bf16)y[e];
+                    *reinterpret_cast<bf16x4*>(base + ol * L::kPitchBf + row[4 * g]) = hi;
                 }
-                *reinterpret_cast<bf16x4*>(base + ol * L::kPitchBf + row[4 * g]) = hi;
-                if constexpr (MODE == kRnnBf16x3)
-                    *reinterpret_cast<bf16x4*>(base + (kOrbitsPerBlock + ol) * L::kPitchBf + row[4 * g]) = lo;
             }
         }
     };
@@ -221,7 +243,7 @@ __global__ __launch_bounds__(64 * (N / 32)) void rnn_mfma_kernel(const RnnArgs a
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const float f = ((acc[r] - X[r]) + bv[r]);
-            X[r] = (X[r] + f * a.dt) + noise_scale * xi[r];
+            X[r] = __builtin_fmaf(noise_scale, xi[r], __builtin_fmaf(f, a.dt, X[r]));
         }
         publish(cur ^ 1);
         if (k + 1 == next_save) {
