@@ -81,17 +81,19 @@ __device__ __forceinline__ float wrap_rad(float x)
 template <int P, int K>
 __device__ __forceinline__ void couple_across(const float (&phi)[P], float (&acc)[P])
 {
-    float other[P], back[P];
+    float back[P];
+    // Partner phase b, then its P uses right after it: the compiler folds a
+    // DPP move into its uses (v_sub_f32_dpp) only when they follow within a
+    // few instructions.  Every sum still takes its terms in the same order
+    // (acc[a] over b, back[b] over a).  back[b] starts from its first term
+    // (0 + s is not an identity under IEEE signed zeros, so a zero start
+    // would cost an add per b).
 #pragma unroll
-    for (int b = 0; b < P; ++b)
-        other[b] = row_rotate<16 - K>(phi[b]);
-    // back[b] starts from its first term (0 + s is not an identity under
-    // IEEE signed zeros, so a zero start would cost an add per b).
+    for (int b = 0; b < P; ++b) {
+        const float other = row_rotate<16 - K>(phi[b]);
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-#pragma unroll
-        for (int b = 0; b < P; ++b) {
-            const float s = sin_rev(other[b] - phi[a]);
+        for (int a = 0; a < P; ++a) {
+            const float s = sin_rev(other - phi[a]);
             acc[a] += s;
             back[b] = a == 0 ? s : back[b] + s;
         }
@@ -132,16 +134,14 @@ __device__ __forceinline__ void coupling_sums(const float (&phi)[P], float (&acc
         }
     }
     couple_rotations<P, 1>(phi, acc);
-    // Opposite lane (rotation by 8 is its own inverse): each side adds its own.
-    float other[P];
+    // Opposite lane (rotation by 8 is its own inverse): each side adds its own,
+    // partner phase by partner phase as above.
 #pragma unroll
-    for (int b = 0; b < P; ++b)
-        other[b] = row_rotate<8>(phi[b]);
+    for (int b = 0; b < P; ++b) {
+        const float other = row_rotate<8>(phi[b]);
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-#pragma unroll
-        for (int b = 0; b < P; ++b)
-            acc[a] += sin_rev(other[b] - phi[a]);
+        for (int a = 0; a < P; ++a)
+            acc[a] += sin_rev(other - phi[a]);
     }
 }
 
