@@ -17,6 +17,12 @@
 // stored.  Long chains spread over many lanes keep the per-step dependency
 // chain short: a batch cannot finish before its longest instance.
 //
+// Noise.  The normals of a step do not depend on the state and are drawn
+// ahead of it.  With two units per lane, lanes 2m and 2m+1 take the two
+// halves of one Philox block; each of them evaluates that block for one of
+// two consecutive steps and the pair swaps halves by DPP, so the block is
+// computed once per step and pair instead of once per lane.
+//
 // Precision.  Near rest the recovery variable moves by ~1e-7 per step,
 // below half a binary32 ulp of w ~ 0.6, so plain binary32 updates stall and
 // drift over 10^5 steps.  With compensation (the handle's default) v and w
@@ -55,6 +61,13 @@ __device__ __forceinline__ float from_upper_lane(float v) { return dpp_read<0x10
 __device__ __forceinline__ float from_lower_lane_wave(float v) { return dpp_read<0x138>(v); }
 __device__ __forceinline__ float from_upper_lane_wave(float v) { return dpp_read<0x130>(v); }
 
+// Value of the other lane of an adjacent pair (lanes 2m, 2m+1): DPP
+// quad_perm [1, 0, 3, 2].
+__device__ __forceinline__ uint32_t from_pair_lane(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
+}
+
 // x_hi + x_lo += inc without losing the rounding error of the sum.
 __device__ __forceinline__ void two_sum_add(float& hi, float& lo, float inc)
 {
@@ -70,7 +83,10 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
 {
     const int slot = lane / L;
     const int l = lane % L;
-    const int32_t inst = a.slots[g * kRaggedSlots + slot];
+    // One instance per wave when L = 64: its descriptor, step count and
+    // parameters are then wave-uniform (scalar loads, a uniform loop).
+    const int32_t inst = L == 64 ? __builtin_amdgcn_readfirstlane(a.slots[g * kRaggedSlots])
+                                 : a.slots[g * kRaggedSlots + slot];
     if (inst < 0)
         return;
     const sode_instance_t d = a.desc[inst];
@@ -81,6 +97,7 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
     const float pa = pr[0], pb = pr[1], eps = pr[2], D = pr[3];
     const float noise = pr[4] * a.sqdt;
     const float dt = a.dt;
+    const float eps_dt = eps * dt;
 
     float v[U], w[U], vlo[U], wlo[U];
 #pragma unroll
@@ -107,18 +124,8 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
     save(0);
     const Stream st{d.orbit_id, (uint32_t)d.seed, (uint32_t)(d.seed >> 32)};
     int64_t s = 1, next_save = d.stride;
-    // The normals do not depend on the state: those of step k+1 are drawn
-    // while step k's state update is in flight, off its dependency chain.
-    float xi_next[U];
-    if (d.nsteps > 0)
-        lane_normals<U>(st, 0u, l, xi_next);
-    for (int64_t k = 0; k < d.nsteps; ++k) {
-        float xi[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            xi[u] = xi_next[u];
-        if (k + 1 < d.nsteps)
-            lane_normals<U>(st, (uint32_t)(k + 1), l, xi_next);
+    // One Euler-Maruyama step (Eq. 2) with the normals xi of step k.
+    auto advance = [&](int64_t k, const float (&xi)[U]) {
         float left_edge, right_edge;
         if constexpr (L <= 16) {
             left_edge = from_lower_lane(v[U - 1]);
@@ -135,12 +142,12 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
             float vr = u < U - 1 ? v[u + 1] : right_edge;
             vl = j == 0 ? v[u] : vl;
             vr = j == N - 1 ? v[u] : vr;
-            const float lap = (vl - 2.0f * v[u]) + vr;
-            const float cube = v[u] * v[u] * v[u] * kThird;
-            const float fv = ((v[u] - cube) - w[u]) + D * lap;
-            const float fw = eps * ((v[u] + pa) - pb * w[u]);
-            dv[u] = fv * dt + noise * xi[u];
-            dw[u] = fw * dt;
+            const float lap = __builtin_fmaf(-2.0f, v[u], vl) + vr;
+            const float cube = (v[u] * v[u]) * (v[u] * kThird);
+            const float fv = __builtin_fmaf(D, lap, (v[u] - cube) - w[u]);
+            const float fw = __builtin_fmaf(-pb, w[u], v[u] + pa);
+            dv[u] = __builtin_fmaf(noise, xi[u], fv * dt);
+            dw[u] = fw * eps_dt;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -156,6 +163,53 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
             save(s);
             ++s;
             next_save += d.stride;
+        }
+    };
+    // The normals do not depend on the state: they are drawn ahead, off the
+    // state's dependency chain.
+    if constexpr (U == 2) {
+        // Lanes 2m and 2m+1 use the two halves of the same Philox block
+        // (block m, words 0-1 and 2-3).  Over two steps each lane of the
+        // pair evaluates the block once, the even lane for the first step and
+        // the odd lane for the second, and the pair swaps the halves it does
+        // not keep: half the Philox work, the same normals.
+        const bool odd = (l & 1) != 0;
+        auto draw_two = [&](int64_t k, float (&xa)[U], float (&xb)[U]) {
+            const Block4 wd =
+                philox_4x32_10((uint32_t)(k + (odd ? 1 : 0)), st.oid, (uint32_t)(l >> 1), 0u, st.key_lo, st.key_hi);
+            const uint32_t own0 = odd ? wd.w2 : wd.w0, own1 = odd ? wd.w3 : wd.w1;
+            const uint32_t got0 = from_pair_lane(odd ? wd.w0 : wd.w2);
+            const uint32_t got1 = from_pair_lane(odd ? wd.w1 : wd.w3);
+            box_muller_f32(odd ? got0 : own0, odd ? got1 : own1, xa[0], xa[1]);  // step k
+            box_muller_f32(odd ? own0 : got0, odd ? own1 : got1, xb[0], xb[1]);  // step k + 1
+        };
+        float xa[U], xb[U];
+        draw_two(0, xa, xb);
+        for (int64_t k = 0; k < d.nsteps; k += 2) {
+            float na[U], nb[U];
+            draw_two(k + 2, na, nb);
+            advance(k, xa);
+            if (k + 1 < d.nsteps)
+                advance(k + 1, xb);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                xa[u] = na[u];
+                xb[u] = nb[u];
+            }
+        }
+    } else {
+        // Normals of step k+1 are drawn while step k's update is in flight.
+        float xi_next[U];
+        if (d.nsteps > 0)
+            lane_normals<U>(st, 0u, l, xi_next);
+        for (int64_t k = 0; k < d.nsteps; ++k) {
+            float xi[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                xi[u] = xi_next[u];
+            if (k + 1 < d.nsteps)
+                lane_normals<U>(st, (uint32_t)(k + 1), l, xi_next);
+            advance(k, xi);
         }
     }
 }

@@ -139,3 +139,33 @@ def test_edge_instances(gpu):
         got = b.unpack(out, i)
         assert got.shape == ref.shape
         assert np.abs(got - ref).max() / max(1.0, np.abs(ref).max()) <= 1e-4
+
+
+def test_odd_step_counts_across_shapes(gpu):
+    """Odd step counts end on a single step after the two-step noise
+    batches of two-units-per-lane shapes; every shape must still agree bit
+    for bit, and with the oracle."""
+    import paper_1908_03869_amd as sode
+    rng = np.random.default_rng(23)
+    units = np.array([2, 4, 64, 125, 3, 40])
+    steps = np.array([1, 3, 333, 77, 999, 5])
+    strides = np.array([1, 3, 111, 7, 333, 5])
+    n = 2 * units
+    b = sode.RaggedBatch(n, steps, strides, np.arange(6) + 5, np.arange(6) * 7 + 1, d=5)
+    X0s = [np.concatenate([-1.2 + 0.1 * rng.standard_normal(u), -0.62 + 0.1 * rng.standard_normal(u)])
+           for u in units]
+    ps = [np.array([0.7, 0.8, 0.08, 0.1, 0.05]) * rng.uniform(0.8, 1.2, 5) for _ in units]
+    X0, p = b.pack(X0s), b.pack(ps)
+    log("ragged odd step counts, units_per_lane 1, 2, 4, 8")
+    ref, _ = _run(b, X0, p, 1e-3, persistent=0, graph=0, units_per_lane=1, waves_per_cu=4)
+    for upl in (2, 4, 8):
+        got, _ = _run(b, X0, p, 1e-3, persistent=1, graph=0, units_per_lane=upl, waves_per_cu=8)
+        np.testing.assert_array_equal(got, ref, err_msg=f"units_per_lane={upl}")
+    X0r, pr = as_received(X0, 32), as_received(p, 32)
+    for i in range(6):
+        a = int(b.x0_offset[i])
+        oref = _oracle_instance((X0r[a:a + n[i]], pr[5 * i:5 * i + 5], int(n[i]), int(steps[i]),
+                                 int(strides[i]), 5 + i, 7 * i + 1))
+        got = b.unpack(ref, i)
+        assert got.shape == oref.shape
+        assert np.abs(got - oref).max() / max(1.0, np.abs(oref).max()) <= 1e-4
