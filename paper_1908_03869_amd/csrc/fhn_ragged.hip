@@ -21,7 +21,9 @@
 // ahead of it.  With two units per lane, lanes 2m and 2m+1 take the two
 // halves of one Philox block; each of them evaluates that block for one of
 // two consecutive steps and the pair swaps halves by DPP, so the block is
-// computed once per step and pair instead of once per lane.
+// computed once per step and pair instead of once per lane.  With one unit
+// per lane the four lanes of a quad share a block the same way over four
+// steps.
 //
 // Precision.  Near rest the recovery variable moves by ~1e-7 per step,
 // below half a binary32 ulp of w ~ 0.6, so plain binary32 updates stall and
@@ -66,6 +68,14 @@ __device__ __forceinline__ float from_upper_lane_wave(float v) { return dpp_read
 __device__ __forceinline__ uint32_t from_pair_lane(uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
+}
+
+// Value of lane S of the lane's quad (DPP quad_perm [S, S, S, S]).
+template <int S>
+__device__ __forceinline__ float from_quad_lane(float v)
+{
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x55 * S, 0xF, 0xF, true));
 }
 
 // x_hi + x_lo += inc without losing the rounding error of the sum.
@@ -197,6 +207,48 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
                 xb[u] = nb[u];
             }
         }
+    } else if constexpr (U == 1) {
+        // The four lanes of a quad use the four normals of one Philox block
+        // (block m for lanes 4m .. 4m+3).  Over four steps lane i of the
+        // quad evaluates that block for step k+i and forms all four normals;
+        // each lane then takes its own normal of every step from the lane
+        // that drew it (DPP broadcasts within the quad): a quarter of the
+        // Philox work and half the Box-Muller work, the same normals.
+        const int qi = l & 3;
+        auto draw_four = [&](int64_t k, float (&x)[4]) {
+            const Block4 wd =
+                philox_4x32_10((uint32_t)(k + qi), st.oid, (uint32_t)(l >> 2), 0u, st.key_lo, st.key_hi);
+            float z[4];
+            box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
+            box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+            auto mine = [&](float c0, float c1, float c2, float c3) {
+                return (qi & 2) ? ((qi & 1) ? c3 : c2) : ((qi & 1) ? c1 : c0);
+            };
+            x[0] = mine(from_quad_lane<0>(z[0]), from_quad_lane<0>(z[1]), from_quad_lane<0>(z[2]),
+                        from_quad_lane<0>(z[3]));
+            x[1] = mine(from_quad_lane<1>(z[0]), from_quad_lane<1>(z[1]), from_quad_lane<1>(z[2]),
+                        from_quad_lane<1>(z[3]));
+            x[2] = mine(from_quad_lane<2>(z[0]), from_quad_lane<2>(z[1]), from_quad_lane<2>(z[2]),
+                        from_quad_lane<2>(z[3]));
+            x[3] = mine(from_quad_lane<3>(z[0]), from_quad_lane<3>(z[1]), from_quad_lane<3>(z[2]),
+                        from_quad_lane<3>(z[3]));
+        };
+        float xc[4];
+        draw_four(0, xc);
+        for (int64_t k = 0; k < d.nsteps; k += 4) {
+            float xn[4];
+            draw_four(k + 4, xn);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t == 0 || k + t < d.nsteps) {
+                    const float xi[1] = {xc[t]};
+                    advance(k + t, xi);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                xc[t] = xn[t];
+        }
     } else {
         // Normals of step k+1 are drawn while step k's update is in flight.
         float xi_next[U];
@@ -214,10 +266,27 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
     }
 }
 
+// Issue priority of the wave among the waves of its SIMD (s_setprio takes
+// an immediate).
+__device__ __forceinline__ void set_wave_priority(int p)
+{
+    if (p >= 3)
+        __builtin_amdgcn_s_setprio(3);
+    else if (p == 2)
+        __builtin_amdgcn_s_setprio(2);
+    else if (p == 1)
+        __builtin_amdgcn_s_setprio(1);
+    else
+        __builtin_amdgcn_s_setprio(0);
+}
+
+// Shape word of a group: shape code in bits 0-7, issue priority in bits 8-9.
 template <bool COMP>
 __device__ __forceinline__ void run_shape(const RaggedKernelArgs& a, int32_t g, int lane)
 {
-    switch (a.shape[g]) {
+    const int32_t word = __builtin_amdgcn_readfirstlane(a.shape[g]);
+    set_wave_priority((word >> 8) & 3);
+    switch (word & 0xFF) {
     case 0: run_group<4, 1, COMP>(a, g, lane); break;
     case 1: run_group<4, 2, COMP>(a, g, lane); break;
     case 2: run_group<4, 4, COMP>(a, g, lane); break;

@@ -113,7 +113,7 @@ constexpr int kRaggedShapes = 20;  // L in {4, 8, 16, 32, 64} x U in {1, 2, 4, 8
 struct RaggedKernelArgs {
     const sode_instance_t* desc;  // device copy of the descriptors
     const int32_t* slots;         // [ngroups][kRaggedSlots] instance index or -1
-    const int32_t* shape;         // [ngroups] shape code (ragged_shape_code)
+    const int32_t* shape;         // [ngroups] shape code (ragged_shape_code) | issue priority << 8
     uint32_t* counter;            // queue ticket counter
     int32_t ngroups;
     const float* X0;

@@ -128,8 +128,15 @@ void build_plan(const sode_instance_t* inst, int32_t count, int units_min, HostP
     });
     plan.slots.assign(groups.size() * kRaggedSlots, -1);
     plan.shape.resize(groups.size());
+    // Issue priority of the wave that runs a group (bits 8-9 of its shape
+    // word): 3 for groups within 2x of the heaviest, 2 within 4x, 1 within
+    // 8x, else 0.  The heaviest chains bound the makespan; the waves that
+    // share their SIMDs fill the cycles they leave.
+    const int64_t top = groups.empty() ? 1 : std::max<int64_t>(groups[0].cost, 1);
     for (size_t g = 0; g < groups.size(); ++g) {
-        plan.shape[g] = groups[g].shape;
+        const int64_t c = groups[g].cost;
+        const int prio = 2 * c >= top ? 3 : 4 * c >= top ? 2 : 8 * c >= top ? 1 : 0;
+        plan.shape[g] = groups[g].shape | (prio << 8);
         for (size_t t = 0; t < groups[g].members.size(); ++t)
             plan.slots[g * kRaggedSlots + t] = groups[g].members[t];
     }
