@@ -18,12 +18,9 @@
 // chain short: a batch cannot finish before its longest instance.
 //
 // Noise.  The normals of a step do not depend on the state and are drawn
-// ahead of it.  With two units per lane, lanes 2m and 2m+1 take the two
-// halves of one Philox block; each of them evaluates that block for one of
-// two consecutive steps and the pair swaps halves by DPP, so the block is
-// computed once per step and pair instead of once per lane.  With one unit
-// per lane the four lanes of a quad share a block the same way over four
-// steps.
+// ahead of it.  With one or two units per lane, a quad or pair of lanes
+// shares each Philox block: lane_normals_steps draws 4 or 2 steps at once,
+// every block evaluated by one lane and passed on by DPP.
 //
 // Precision.  Near rest the recovery variable moves by ~1e-7 per step,
 // below half a binary32 ulp of w ~ 0.6, so plain binary32 updates stall and
@@ -62,21 +59,6 @@ __device__ __forceinline__ float from_upper_lane(float v) { return dpp_read<0x10
 // DPP form), one VALU operation instead of an LDS permute round trip.
 __device__ __forceinline__ float from_lower_lane_wave(float v) { return dpp_read<0x138>(v); }
 __device__ __forceinline__ float from_upper_lane_wave(float v) { return dpp_read<0x130>(v); }
-
-// Value of the other lane of an adjacent pair (lanes 2m, 2m+1): DPP
-// quad_perm [1, 0, 3, 2].
-__device__ __forceinline__ uint32_t from_pair_lane(uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
-}
-
-// Value of lane S of the lane's quad (DPP quad_perm [S, S, S, S]).
-template <int S>
-__device__ __forceinline__ float from_quad_lane(float v)
-{
-    return __builtin_bit_cast(float,
-                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x55 * S, 0xF, 0xF, true));
-}
 
 // x_hi + x_lo += inc without losing the rounding error of the sum.
 __device__ __forceinline__ void two_sum_add(float& hi, float& lo, float inc)
@@ -177,77 +159,26 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
     };
     // The normals do not depend on the state: they are drawn ahead, off the
     // state's dependency chain.
-    if constexpr (U == 2) {
-        // Lanes 2m and 2m+1 use the two halves of the same Philox block
-        // (block m, words 0-1 and 2-3).  Over two steps each lane of the
-        // pair evaluates the block once, the even lane for the first step and
-        // the odd lane for the second, and the pair swaps the halves it does
-        // not keep: half the Philox work, the same normals.
-        const bool odd = (l & 1) != 0;
-        auto draw_two = [&](int64_t k, float (&xa)[U], float (&xb)[U]) {
-            const Block4 wd =
-                philox_4x32_10((uint32_t)(k + (odd ? 1 : 0)), st.oid, (uint32_t)(l >> 1), 0u, st.key_lo, st.key_hi);
-            const uint32_t own0 = odd ? wd.w2 : wd.w0, own1 = odd ? wd.w3 : wd.w1;
-            const uint32_t got0 = from_pair_lane(odd ? wd.w0 : wd.w2);
-            const uint32_t got1 = from_pair_lane(odd ? wd.w1 : wd.w3);
-            box_muller_f32(odd ? got0 : own0, odd ? got1 : own1, xa[0], xa[1]);  // step k
-            box_muller_f32(odd ? own0 : got0, odd ? own1 : got1, xb[0], xb[1]);  // step k + 1
-        };
-        float xa[U], xb[U];
-        draw_two(0, xa, xb);
-        for (int64_t k = 0; k < d.nsteps; k += 2) {
-            float na[U], nb[U];
-            draw_two(k + 2, na, nb);
-            advance(k, xa);
-            if (k + 1 < d.nsteps)
-                advance(k + 1, xb);
+    if constexpr (U <= 2) {
+        // One or two units per lane: the normals of B = 4/U steps at a time,
+        // one Philox block per quad (U = 1) or pair (U = 2) of lanes and step
+        // (lane_normals_steps), drawn one batch ahead.
+        constexpr int B = 4 / U;
+        float xc[B][U];
+        lane_normals_steps<U>(st, 0u, l, xc);
+        for (int64_t k = 0; k < d.nsteps; k += B) {
+            float xn[B][U];
+            lane_normals_steps<U>(st, (uint32_t)(k + B), l, xn);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                xa[u] = na[u];
-                xb[u] = nb[u];
-            }
-        }
-    } else if constexpr (U == 1) {
-        // The four lanes of a quad use the four normals of one Philox block
-        // (block m for lanes 4m .. 4m+3).  Over four steps lane i of the
-        // quad evaluates that block for step k+i and forms all four normals;
-        // each lane then takes its own normal of every step from the lane
-        // that drew it (DPP broadcasts within the quad): a quarter of the
-        // Philox work and half the Box-Muller work, the same normals.
-        const int qi = l & 3;
-        auto draw_four = [&](int64_t k, float (&x)[4]) {
-            const Block4 wd =
-                philox_4x32_10((uint32_t)(k + qi), st.oid, (uint32_t)(l >> 2), 0u, st.key_lo, st.key_hi);
-            float z[4];
-            box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
-            box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
-            auto mine = [&](float c0, float c1, float c2, float c3) {
-                return (qi & 2) ? ((qi & 1) ? c3 : c2) : ((qi & 1) ? c1 : c0);
-            };
-            x[0] = mine(from_quad_lane<0>(z[0]), from_quad_lane<0>(z[1]), from_quad_lane<0>(z[2]),
-                        from_quad_lane<0>(z[3]));
-            x[1] = mine(from_quad_lane<1>(z[0]), from_quad_lane<1>(z[1]), from_quad_lane<1>(z[2]),
-                        from_quad_lane<1>(z[3]));
-            x[2] = mine(from_quad_lane<2>(z[0]), from_quad_lane<2>(z[1]), from_quad_lane<2>(z[2]),
-                        from_quad_lane<2>(z[3]));
-            x[3] = mine(from_quad_lane<3>(z[0]), from_quad_lane<3>(z[1]), from_quad_lane<3>(z[2]),
-                        from_quad_lane<3>(z[3]));
-        };
-        float xc[4];
-        draw_four(0, xc);
-        for (int64_t k = 0; k < d.nsteps; k += 4) {
-            float xn[4];
-            draw_four(k + 4, xn);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (t == 0 || k + t < d.nsteps) {
-                    const float xi[1] = {xc[t]};
-                    advance(k + t, xi);
-                }
+            for (int t = 0; t < B; ++t) {
+                if (t == 0 || k + t < d.nsteps)
+                    advance(k + t, xc[t]);
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                xc[t] = xn[t];
+            for (int t = 0; t < B; ++t)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    xc[t][u] = xn[t][u];
         }
     } else {
         // Normals of step k+1 are drawn while step k's update is in flight.

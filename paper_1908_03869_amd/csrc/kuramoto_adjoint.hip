@@ -90,16 +90,44 @@ __global__ __launch_bounds__(256) void forward_ckpt_kernel(const CkptArgs a)
     }
     // Statistic accumulated in binary64 (every lane holds the row's value).
     double racc = in_window(0, a.win_lo, a.win_hi) ? (double)order_parameter<P>(th) : 0.0;
-    int64_t k = 0;
-    for (int64_t cidx = 1; cidx < a.nckpt; ++cidx) {
-        for (int64_t kk = 0; kk < a.every; ++kk, ++k) {
-            em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)k), l);
-            if (in_window(k + 1, a.win_lo, a.win_hi))
-                racc += (double)order_parameter<P>(th);
-        }
+    if constexpr (P <= 2) {
+        // Normals of B = 4/P steps at a time, one Philox block per quad or
+        // pair of lanes and step (lane_normals_steps).
+        constexpr int B = 4 / P;
+        const int64_t nsteps = (a.nckpt - 1) * a.every;
+        int64_t cidx = 1, to_ckpt = a.every;
+        for (int64_t j = 0; j < nsteps; j += B) {
+            float xb[B][P];
+            lane_normals_steps<P>(st, (uint32_t)(a.step_offset + (uint64_t)j), l, xb);
 #pragma unroll
-        for (int i = 0; i < P; ++i)
-            ck[cidx * N + i] = th[i];
+            for (int t = 0; t < B; ++t) {
+                const int64_t k = j + t;
+                if (t == 0 || k < nsteps) {
+                    em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)k), l, nullptr, xb[t]);
+                    if (in_window(k + 1, a.win_lo, a.win_hi))
+                        racc += (double)order_parameter<P>(th);
+                    if (--to_ckpt == 0) {
+#pragma unroll
+                        for (int i = 0; i < P; ++i)
+                            ck[cidx * N + i] = th[i];
+                        ++cidx;
+                        to_ckpt = a.every;
+                    }
+                }
+            }
+        }
+    } else {
+        int64_t k = 0;
+        for (int64_t cidx = 1; cidx < a.nckpt; ++cidx) {
+            for (int64_t kk = 0; kk < a.every; ++kk, ++k) {
+                em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)k), l);
+                if (in_window(k + 1, a.win_lo, a.win_hi))
+                    racc += (double)order_parameter<P>(th);
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                ck[cidx * N + i] = th[i];
+        }
     }
     if (l == 0)
         a.R[o] = racc * a.inv_window;
@@ -174,14 +202,35 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjointArgs a)
             th[i] = ck[cidx * N + i];
             tl[i] = 0.0f;
         }
-        for (int64_t j = 0; j < a.every; ++j) {
-            float* __restrict__ rec = seg + j * 16 * (2 * P);
+        if constexpr (P <= 2) {
+            constexpr int B = 4 / P;
+            for (int64_t j0 = 0; j0 < a.every; j0 += B) {
+                float xb[B][P];
+                lane_normals_steps<P>(st, (uint32_t)(a.step_offset + (uint64_t)(kbase + j0)), l, xb);
 #pragma unroll
-            for (int i = 0; i < P; ++i)
-                rec[i] = th[i];
-            if (j + 1 < a.every)
-                em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)(kbase + j)), l,
-                                     rec + P);
+                for (int t = 0; t < B; ++t) {
+                    const int64_t j = j0 + t;
+                    if (t == 0 || j < a.every) {
+                        float* __restrict__ rec = seg + j * 16 * (2 * P);
+#pragma unroll
+                        for (int i = 0; i < P; ++i)
+                            rec[i] = th[i];
+                        if (j + 1 < a.every)
+                            em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)(kbase + j)), l,
+                                                 rec + P, xb[t]);
+                    }
+                }
+            }
+        } else {
+            for (int64_t j = 0; j < a.every; ++j) {
+                float* __restrict__ rec = seg + j * 16 * (2 * P);
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    rec[i] = th[i];
+                if (j + 1 < a.every)
+                    em_step<P, COMP, MF>(th, tl, c, st, (uint32_t)(a.step_offset + (uint64_t)(kbase + j)), l,
+                                         rec + P);
+            }
         }
         // Reverse sweep over the segment.  The record of step j - 1 is
         // loaded while step j is processed, off the dependency chain.

@@ -82,10 +82,34 @@ __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs
 
     save<P, PAD>(a, l, th, c, out_row, 0);
     uint32_t k = (uint32_t)a.step_offset;
-    for (int64_t s = 1; s < a.nsave; ++s) {
-        for (int64_t kk = 0; kk < a.stride; ++kk, ++k)
-            em_step<P, COMP, MF, PAD>(th, tl, c, st, k, l);
-        save<P, PAD>(a, l, th, c, out_row, s);
+    if constexpr (P <= 2) {
+        // One Philox block per quad (P = 1) or pair (P = 2) of lanes and
+        // step: the normals of B = 4/P steps at a time (lane_normals_steps).
+        constexpr int B = 4 / P;
+        const int64_t nsteps = (a.nsave - 1) * a.stride;
+        int64_t s = 1, to_save = a.stride;
+        for (int64_t j = 0; j < nsteps; j += B) {
+            float xb[B][P];
+            lane_normals_steps<P>(st, k, l, xb);
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                if (t == 0 || j + t < nsteps) {
+                    em_step<P, COMP, MF, PAD>(th, tl, c, st, k, l, nullptr, xb[t]);
+                    ++k;
+                    if (--to_save == 0) {
+                        save<P, PAD>(a, l, th, c, out_row, s);
+                        ++s;
+                        to_save = a.stride;
+                    }
+                }
+            }
+        }
+    } else {
+        for (int64_t s = 1; s < a.nsave; ++s) {
+            for (int64_t kk = 0; kk < a.stride; ++kk, ++k)
+                em_step<P, COMP, MF, PAD>(th, tl, c, st, k, l);
+            save<P, PAD>(a, l, th, c, out_row, s);
+        }
     }
 }
 

@@ -228,10 +228,12 @@ __device__ __forceinline__ void mean_field_sums(const float (&phi)[P], float (&a
 // increment and the old trailing part are added with an error-free two-sum,
 // and a wrap moves the tail of 2 pi into tl.  MF: coupling through the
 // mean-field identity instead of pairwise sines.  PAD: see the top of the file.
-// xi_out (optional) receives the step's P normals.
+// xi_out (optional) receives the step's P normals; xi_in (optional) supplies
+// them, already drawn (lane_normals_steps), instead of lane_normals.
 template <int P, bool COMP, bool MF = false, bool PAD = false>
 __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const LaneCoefficients<P, PAD>& c,
-                                        const Stream& st, uint32_t k, int l, float* xi_out = nullptr)
+                                        const Stream& st, uint32_t k, int l, float* xi_out = nullptr,
+                                        const float* xi_in = nullptr)
 {
     float phi[P], acc[P], xi[P];
 #pragma unroll
@@ -247,7 +249,13 @@ __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const La
                 acc[i] = __builtin_fmaf(c.pads, sin_rev(phi[i]), acc[i]);
         }
     }
-    lane_normals<P>(st, k, l, xi);
+    if (xi_in) {
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            xi[i] = xi_in[i];
+    } else {
+        lane_normals<P>(st, k, l, xi);
+    }
     if (xi_out) {  // the step's normals, for a caller that needs them again
 #pragma unroll
         for (int i = 0; i < P; ++i)

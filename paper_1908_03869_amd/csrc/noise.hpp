@@ -176,4 +176,57 @@ __device__ __forceinline__ void lane_normals(const Stream& st, uint32_t k, int l
     }
 }
 
+// Value held by another lane of the same quad of lanes (DPP quad_perm):
+// the other lane of an adjacent pair (2m, 2m+1), or lane S of the quad.
+__device__ __forceinline__ uint32_t from_pair_lane(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
+}
+template <int S>
+__device__ __forceinline__ float from_quad_lane(float v)
+{
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x55 * S, 0xF, 0xF, true));
+}
+
+// The normals of lane_normals<P> for the 4/P consecutive steps k .. k+4/P-1
+// at once, xi[t] being those of step k+t (P = 1 or 2).  Lanes 4m .. 4m+3
+// (P = 1) or 2m, 2m+1 (P = 2) use one Philox block per step between them;
+// here each of them evaluates that block for one of the steps and passes
+// on the words or normals the others need through DPP, so every block is
+// computed once instead of once per lane: the same values, 1/4 or 1/2 of
+// the Philox work (and half the Box-Muller work for P = 1).  The lanes of a
+// quad must belong to the same orbit and be active together.
+template <int P>
+__device__ __forceinline__ void lane_normals_steps(const Stream& st, uint32_t k, int l, float (&xi)[4 / P][P])
+{
+    static_assert(P == 1 || P == 2, "lanes per Philox block");
+    if constexpr (P == 2) {
+        const bool odd = (l & 1) != 0;
+        const Block4 w = philox_4x32_10(k + (odd ? 1u : 0u), st.oid, (uint32_t)(l >> 1), 0u, st.key_lo, st.key_hi);
+        // Even lane: block of step k, keeps words 0-1, passes 2-3.  Odd lane:
+        // block of step k+1, keeps words 2-3, passes 0-1.
+        const uint32_t own0 = odd ? w.w2 : w.w0, own1 = odd ? w.w3 : w.w1;
+        const uint32_t got0 = from_pair_lane(odd ? w.w0 : w.w2);
+        const uint32_t got1 = from_pair_lane(odd ? w.w1 : w.w3);
+        box_muller_f32(odd ? got0 : own0, odd ? got1 : own1, xi[0][0], xi[0][1]);
+        box_muller_f32(odd ? own0 : got0, odd ? own1 : got1, xi[1][0], xi[1][1]);
+    } else {
+        // Lane i of the quad draws all four normals of step k+i; normal j of
+        // a step belongs to lane j.
+        const int qi = l & 3;
+        const Block4 w = philox_4x32_10(k + (uint32_t)qi, st.oid, (uint32_t)(l >> 2), 0u, st.key_lo, st.key_hi);
+        float z0, z1, z2, z3;
+        box_muller_f32(w.w0, w.w1, z0, z1);
+        box_muller_f32(w.w2, w.w3, z2, z3);
+        auto mine = [qi](float c0, float c1, float c2, float c3) {
+            return (qi & 2) ? ((qi & 1) ? c3 : c2) : ((qi & 1) ? c1 : c0);
+        };
+        xi[0][0] = mine(from_quad_lane<0>(z0), from_quad_lane<0>(z1), from_quad_lane<0>(z2), from_quad_lane<0>(z3));
+        xi[1][0] = mine(from_quad_lane<1>(z0), from_quad_lane<1>(z1), from_quad_lane<1>(z2), from_quad_lane<1>(z3));
+        xi[2][0] = mine(from_quad_lane<2>(z0), from_quad_lane<2>(z1), from_quad_lane<2>(z2), from_quad_lane<2>(z3));
+        xi[3][0] = mine(from_quad_lane<3>(z0), from_quad_lane<3>(z1), from_quad_lane<3>(z2), from_quad_lane<3>(z3));
+    }
+}
+
 }  // namespace sode
