@@ -164,10 +164,10 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  of 16 runs padded with oscillators frozen at phase 0
  *                  whose coupling is cancelled); 3 = matrix (see "gemm").
  *                  Auto takes coupled for binary32 Kuramoto EM with
- *                  8 <= n <= 128 (n < 8: only up to 65,536 orbits) and for
+ *                  5 <= n <= 128 (n < 5: only up to 65,536 orbits) and for
  *                  binary64 Kuramoto EM with n <= 16 where it is faster
- *                  (pairwise: n >= 12 or up to 400 n^2 orbits; mean-field:
- *                  up to 16,384 orbits), matrix for a supported dense
+ *                  (n >= 10, else up to 400 n^2 orbits pairwise or 65,536
+ *                  orbits mean-field), matrix for a supported dense
  *                  network, else plain.
  *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
  *                  used by every orbit.

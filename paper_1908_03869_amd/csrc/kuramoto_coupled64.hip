@@ -116,19 +116,77 @@ __device__ __forceinline__ void coupling_sums64(const double (&th)[P], double (&
 template <int P>
 __device__ __forceinline__ void lane_normals64(const Stream& st, uint32_t k, int l, double (&xi)[P])
 {
-    constexpr int NB = (P + 6) / 4;  // ceil((P + 3) / 4) blocks at most
-    const int j0 = P * l;
-    const int off = j0 & 3;
-    double z[4 * NB];
+    if constexpr (P % 4 == 0) {  // whole blocks P l / 4 .. P l / 4 + P / 4 - 1
 #pragma unroll
-    for (int g = 0; g < NB; ++g) {
-        const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)((j0 >> 2) + g), 0u, st.key_lo, st.key_hi);
-        box_muller_f64(w.w0, w.w1, z[4 * g + 0], z[4 * g + 1]);
-        box_muller_f64(w.w2, w.w3, z[4 * g + 2], z[4 * g + 3]);
+        for (int g = 0; g < P / 4; ++g) {
+            const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)((P / 4) * l + g), 0u, st.key_lo, st.key_hi);
+            box_muller_f64(w.w0, w.w1, xi[4 * g + 0], xi[4 * g + 1]);
+            box_muller_f64(w.w2, w.w3, xi[4 * g + 2], xi[4 * g + 3]);
+        }
+    } else {
+        constexpr int NB = (P + 6) / 4;  // ceil((P + 3) / 4) blocks at most
+        const int j0 = P * l;
+        const int off = j0 & 3;
+        double z[4 * NB];
+#pragma unroll
+        for (int g = 0; g < NB; ++g) {
+            const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)((j0 >> 2) + g), 0u, st.key_lo, st.key_hi);
+            box_muller_f64(w.w0, w.w1, z[4 * g + 0], z[4 * g + 1]);
+            box_muller_f64(w.w2, w.w3, z[4 * g + 2], z[4 * g + 3]);
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            xi[i] = off == 0 ? z[i] : off == 1 ? z[i + 1] : off == 2 ? z[i + 2] : z[i + 3];
     }
-#pragma unroll
-    for (int i = 0; i < P; ++i)
-        xi[i] = off == 0 ? z[i] : off == 1 ? z[i + 1] : off == 2 ? z[i + 2] : z[i + 3];
+}
+
+// A binary64 value held by lane S of the lane's quad (two DPP quad_perm
+// moves of the 32-bit halves).
+template <int S>
+__device__ __forceinline__ double from_quad_lane64(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x55 * S, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x55 * S, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// lane_normals64<P> of the 4/P consecutive steps k .. k+4/P-1 at once
+// (P = 1 or 2), xi[t] being those of step k+t: the lanes of a quad (P = 1)
+// or pair (P = 2) need the normals of one Philox block per step, so each
+// evaluates the block of one of the steps (and its Box-Muller pairs) and
+// passes on what the others need through DPP.  The same values with 1/4 or
+// 1/2 of the Philox work and 1/4 or 1/2 of the binary64 Box-Muller work.
+template <int P>
+__device__ __forceinline__ void lane_normals64_steps(const Stream& st, uint32_t k, int l, double (&xi)[4 / P][P])
+{
+    static_assert(P == 1 || P == 2, "lanes per Philox block");
+    if constexpr (P == 2) {
+        const bool odd = (l & 1) != 0;
+        const Block4 w = philox_4x32_10(k + (odd ? 1u : 0u), st.oid, (uint32_t)(l >> 1), 0u, st.key_lo, st.key_hi);
+        const uint32_t own0 = odd ? w.w2 : w.w0, own1 = odd ? w.w3 : w.w1;
+        const uint32_t got0 = from_pair_lane(odd ? w.w0 : w.w2);
+        const uint32_t got1 = from_pair_lane(odd ? w.w1 : w.w3);
+        box_muller_f64(odd ? got0 : own0, odd ? got1 : own1, xi[0][0], xi[0][1]);
+        box_muller_f64(odd ? own0 : got0, odd ? own1 : got1, xi[1][0], xi[1][1]);
+    } else {
+        const int qi = l & 3;
+        const Block4 w = philox_4x32_10(k + (uint32_t)qi, st.oid, (uint32_t)(l >> 2), 0u, st.key_lo, st.key_hi);
+        double z0, z1, z2, z3;
+        box_muller_f64(w.w0, w.w1, z0, z1);
+        box_muller_f64(w.w2, w.w3, z2, z3);
+        auto mine = [qi](double c0, double c1, double c2, double c3) {
+            return (qi & 2) ? ((qi & 1) ? c3 : c2) : ((qi & 1) ? c1 : c0);
+        };
+        xi[0][0] = mine(from_quad_lane64<0>(z0), from_quad_lane64<0>(z1), from_quad_lane64<0>(z2),
+                        from_quad_lane64<0>(z3));
+        xi[1][0] = mine(from_quad_lane64<1>(z0), from_quad_lane64<1>(z1), from_quad_lane64<1>(z2),
+                        from_quad_lane64<1>(z3));
+        xi[2][0] = mine(from_quad_lane64<2>(z0), from_quad_lane64<2>(z1), from_quad_lane64<2>(z2),
+                        from_quad_lane64<2>(z3));
+        xi[3][0] = mine(from_quad_lane64<3>(z0), from_quad_lane64<3>(z1), from_quad_lane64<3>(z2),
+                        from_quad_lane64<3>(z3));
+    }
 }
 
 struct Coupled64Args {
@@ -206,38 +264,67 @@ __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64
         }
     };
 
-    save(0);
-    uint32_t k = (uint32_t)a.step_offset;
-    for (int64_t s = 1; s < a.nsave; ++s) {
-        for (int64_t kk = 0; kk < a.stride; ++kk, ++k) {
-            double acc[P], xi[P];
-            if constexpr (MF) {
-                // sum_j sin(theta_j - theta_i) = cos(theta_i) S - sin(theta_i) C.
-                double cs[P], sn[P], c = 0.0, sv = 0.0;
+    // One Euler-Maruyama step with the normals xi of step k.
+    auto step = [&](const double (&xi)[P]) {
+        double acc[P];
+        if constexpr (MF) {
+            // sum_j sin(theta_j - theta_i) = cos(theta_i) S - sin(theta_i) C.
+            double cs[P], sn[P], c = 0.0, sv = 0.0;
 #pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    sincos(th[i], &sn[i], &cs[i]);
-                    c += cs[i] * w[i];
-                    sv += sn[i] * w[i];
-                }
-                const double C = row_sum64(c), S = row_sum64(sv);
-#pragma unroll
-                for (int i = 0; i < P; ++i)
-                    acc[i] = cs[i] * S - sn[i] * C;
-            } else {
-                coupling_sums64<P>(th, acc);
-                if constexpr (PAD) {
-#pragma unroll
-                    for (int i = 0; i < P; ++i)
-                        acc[i] = fma(pads, sin(th[i]), acc[i]);
-                }
+            for (int i = 0; i < P; ++i) {
+                sincos(th[i], &sn[i], &cs[i]);
+                c += cs[i] * w[i];
+                sv += sn[i] * w[i];
             }
-            lane_normals64<P>(st, k, l, xi);
+            const double C = row_sum64(c), S = row_sum64(sv);
 #pragma unroll
             for (int i = 0; i < P; ++i)
-                th[i] = wrap64(th[i] + (fma(kc[i], acc[i], drift0[i]) + noise[i] * xi[i]));
+                acc[i] = cs[i] * S - sn[i] * C;
+        } else {
+            coupling_sums64<P>(th, acc);
+            if constexpr (PAD) {
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    acc[i] = fma(pads, sin(th[i]), acc[i]);
+            }
         }
-        save(s);
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            th[i] = wrap64(th[i] + (fma(kc[i], acc[i], drift0[i]) + noise[i] * xi[i]));
+    };
+
+    save(0);
+    uint32_t k = (uint32_t)a.step_offset;
+    if constexpr (P <= 2) {
+        // Normals of B = 4/P steps at a time (lane_normals64_steps).
+        constexpr int B = 4 / P;
+        const int64_t nsteps = (a.nsave - 1) * a.stride;
+        int64_t s = 1, to_save = a.stride;
+        for (int64_t j = 0; j < nsteps; j += B) {
+            double xb[B][P];
+            lane_normals64_steps<P>(st, k, l, xb);
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                if (t == 0 || j + t < nsteps) {
+                    step(xb[t]);
+                    ++k;
+                    if (--to_save == 0) {
+                        save(s);
+                        ++s;
+                        to_save = a.stride;
+                    }
+                }
+            }
+        }
+    } else {
+        for (int64_t s = 1; s < a.nsave; ++s) {
+            for (int64_t kk = 0; kk < a.stride; ++kk, ++k) {
+                double xi[P];
+                lane_normals64<P>(st, k, l, xi);
+                step(xi);
+            }
+            save(s);
+        }
     }
 }
 

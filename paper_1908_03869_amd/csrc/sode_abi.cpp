@@ -94,14 +94,16 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
 }
 
 // Which kernel a request goes to; SODE_EUNSUPPORTED if none can run it.
-// Auto: in binary32 the 16-lane Kuramoto kernel wherever it applies, except
-// for fewer than 8 oscillators over many orbits, where a padded row wastes
-// most of its lanes and one orbit per lane fills the chip anyway (measured
-// crossover: between 40,960 and 81,920 orbits at n = 5).  In binary64 the
-// 16-lane kernel for n <= 16 where it measured faster on the paper's speed
-// protocol: pairwise from n = 12 at any size and below that up to 400 n^2
-// orbits (one orbit per lane costs ~n^2 per orbit-step, the padded row a
-// constant), mean-field up to 16,384 orbits; otherwise one orbit per lane.
+// Auto follows the paper's speed protocol as measured here (N = 5, 10, 15,
+// 512 to 163,840 orbits).  Binary32: the 16-lane Kuramoto kernel wherever
+// it applies, except for fewer than 5 oscillators over many orbits, where a
+// padded row wastes most of its lanes and one orbit per lane fills the chip
+// anyway (at n = 5 the 16-lane row is faster at every size measured).
+// Binary64, n <= 16: the 16-lane kernel from n = 10 at any size and below
+// that up to 400 n^2 orbits pairwise (one orbit per lane costs ~n^2 per
+// orbit-step, the padded row a constant; crossover between 5,120 and 25,600
+// orbits at n = 5) or 65,536 orbits mean-field (crossover between 40,960
+// and 81,920 at n = 5); otherwise one orbit per lane.
 int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 {
     if (h->model == sode::kCustom) {
@@ -132,11 +134,10 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
         if (!plain_ok)
             return SODE_EUNSUPPORTED;
         *kernel = 1;
-    } else if (coupled_ok && h->precision == 32 && (h->n >= 8 || orbits <= 65536)) {
+    } else if (coupled_ok && h->precision == 32 && (h->n >= 5 || orbits <= 65536)) {
         *kernel = 2;
     } else if (coupled_ok && h->precision == 64 && h->n <= 16 &&
-               (h->drift == 1 ? orbits <= 16384
-                              : (h->n >= 12 || orbits <= 400 * (int64_t)h->n * h->n))) {
+               (h->n >= 10 || (h->drift == 1 ? orbits <= 65536 : orbits <= 400 * (int64_t)h->n * h->n))) {
         *kernel = 2;
     } else if (matrix_ok) {
         *kernel = 3;
