@@ -33,8 +33,11 @@
 // cost U x steps (longest processing time first).  Waves of the persistent
 // grid pop groups with one atomic counter until the list is exhausted, so
 // the batch is balanced without knowing in advance which instance finishes
-// when.  The same group body also runs non-persistently (one block per
-// group), which gives bitwise the same result.
+// when.  The wave running a group takes an issue priority (s_setprio) from
+// the group's cost relative to the heaviest one, so a critical-path chain
+// that shares a SIMD issues first.  The same group body also runs
+// non-persistently (one block per group), which gives bitwise the same
+// result.
 #include "devmath.hpp"
 #include "launch.hpp"
 #include "noise.hpp"
