@@ -334,8 +334,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(orbits shard trivially by orbit_offset; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; an ensemble "
+              "shards across GPUs by orbit_offset, one process per GPU.", file=sys.stderr)
         sys.exit(2)
 
     import torch

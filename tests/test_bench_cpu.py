@@ -1,0 +1,40 @@
+"""bench.py pieces that run without a GPU: the refusal of a multi-GPU run and
+the algorithmic work the roofline divides by (counted from the method's
+formulation: each unordered oscillator pair once, Philox-4x32-10 and
+Box-Muller per the paper's Eq. 3)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_multi_gpu_request_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+@pytest.mark.parametrize("n", [4, 16, 64, 128])
+def test_algorithmic_slots_count_each_pair_once(n):
+    import bench
+    c = bench.algorithmic_slots_per_orbit_step(n)
+    pairs = n * (n - 1) // 2
+    blocks = (n + 3) // 4
+    bm_pairs = (n + 1) // 2
+    assert c["trans"] == pairs + 4 * bm_pairs          # one sine per pair; log, sqrt, sin, cos per pair of normals
+    assert c["imul"] == 40 * blocks                      # ten rounds x two 32x32 -> 64 products, high and low
+    assert c["valu"] == 3 * pairs + 13 * n + 7 * bm_pairs + 20 * blocks
+    assert c["slots"] == c["valu"] + 4 * c["trans"] + 2 * c["imul"]
+
+
+def test_headline_workload_slot_count():
+    """The n = 64 figure quoted with the roofline: 17,280 slots per orbit-step."""
+    import bench
+    c = bench.algorithmic_slots_per_orbit_step(64)
+    assert (c["valu"], c["trans"], c["imul"], c["slots"]) == (7424, 2144, 640, 17280)
