@@ -11,8 +11,7 @@
  * Build flags: -O2 -ffp-contract=off, no fast-math, glibc libm.  Single
  * threaded.  Every sum runs in index order.  All arithmetic is IEEE binary64.
  *
- * Conventions fixed here where the paper is silent (each is listed with its
- * reason in the design notes of the repository):
+ * Conventions fixed here where the paper is silent:
  *   - the uniform generator is Philox-4x32 with 10 rounds, the counter-based
  *     family the noise-generator section cites (Salmon et al. 2011);
  *   - counter = (global step k, orbit id, noise block b, tag 0),
