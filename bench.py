@@ -195,6 +195,92 @@ def rnn_leg(sode, torch, workloads, dev, gemms=("bf16", "bf16x3", "fp32")) -> di
     return res
 
 
+NEXT_KURAMOTO4_DRIFT = """
+const int N = 4;
+for (int i = 0; i < N; ++i) {
+    real acc = 0;
+    for (int j = 0; j < N; ++j) acc = acc + sin(y[j] - y[i]);
+    f[i] = acc * (p[0] / N) + p[1 + i];
+}
+"""
+NEXT_KURAMOTO4_DIFFUSION = "for (int i = 0; i < 4; ++i) gx[i] = p[5 + i] * xi[i];"
+
+
+def next_rows(sode, torch, dev, reps: int = 3) -> None:
+    """Throughput of the steppers and model paths beyond the hot path, one JSON
+    line per case, kernel time (HIP events, median of `reps` after a warm-up)
+    with inputs resident in HBM: the Milstein stepper against Euler-Maruyama
+    on geometric Brownian motion (n = 1, 2^20 orbits); the implicit steppers
+    against Euler-Maruyama and RK4 on an FHN chain (n = 6) and alone on a
+    stiff OU system (a dt = 10, where the explicit steppers diverge); and the
+    n = 4 Kuramoto system given as source text (run-time compiled) against
+    the same system built in, on the one-orbit-per-lane kernel."""
+    stream = torch.cuda.current_stream()
+
+    def timed(it, X0, p, dt, nsteps, stride):
+        out = it.integrate(X0, p, 0.0, dt, nsteps, stride, 11)
+        it.sync()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            it.integrate(X0, p, 0.0, dt, nsteps, stride, 11, out=out)
+            e1.record(stream)
+            it.sync()
+            times.append(e0.elapsed_time(e1))
+        return float(np.median(times))
+
+    def emit(row, model, prec, method, orbits, nsteps, ms, **extra):
+        line = {"next_row": row, "model": model, "precision": prec, "method": method, "orbits": orbits,
+                "nsteps": nsteps, "kernel_ms": ms, "orbit_steps_per_s": orbits * nsteps / (ms * 1e-3)}
+        line.update(extra)
+        print(json.dumps(line), flush=True)
+
+    rng = np.random.default_rng(17)
+    # Milstein vs Euler-Maruyama, geometric Brownian motion.
+    orbits, nsteps = 1 << 20, 2000
+    for prec, dtype in ((64, torch.float64), (32, torch.float32)):
+        X0 = torch.ones((orbits, 1), dtype=dtype, device=dev)
+        p = torch.tensor([0.5, 0.4], dtype=dtype, device=dev)
+        for method in ("em", "milstein"):
+            it = sode.Integrator("gbm", 1, 1, 2, precision=prec, method=method, kernel="plain", shared_params=1)
+            emit("milstein", "gbm", prec, method, orbits, nsteps, timed(it, X0, p, 1e-3, nsteps, nsteps))
+            it.close()
+    # Implicit steppers: FHN chain of 3 units (n = 6), binary64.
+    orbits, nsteps = 65536, 1000
+    X0 = torch.tensor(rng.uniform(-1.0, 1.0, (orbits, 6)), dtype=torch.float64, device=dev)
+    p = torch.tensor([0.7, 0.8, 0.08, 0.1, 0.05], dtype=torch.float64, device=dev)
+    for method in ("em", "rk4", "implicit_euler", "implicit_midpoint"):
+        it = sode.Integrator("fhn", 6, 3, 5, precision=64, method=method, kernel="plain", shared_params=1)
+        emit("implicit", "fhn_n6", 64, method, orbits, nsteps, timed(it, X0, p, 0.05, nsteps, nsteps))
+        it.close()
+    # Stiff OU (n = 3, a dt = 10): only the implicit steppers are stable.
+    X0 = torch.tensor(rng.uniform(-1.0, 1.0, (orbits, 3)), dtype=torch.float64, device=dev)
+    p = torch.tensor([1000.0, 0.3, 0.5], dtype=torch.float64, device=dev)
+    for method in ("implicit_euler", "implicit_midpoint"):
+        it = sode.Integrator("ou", 3, 3, 3, precision=64, method=method, kernel="plain", shared_params=1)
+        emit("implicit", "ou_stiff_n3", 64, method, orbits, nsteps, timed(it, X0, p, 0.01, nsteps, nsteps))
+        it.close()
+    # Source-text model vs the built-in one: Kuramoto n = 4, binary64.
+    orbits, nsteps = 65536, 2000
+    X0 = torch.tensor(rng.uniform(0.0, 2.0 * math.pi, (orbits, 4)), dtype=torch.float64, device=dev)
+    pk = np.concatenate([[2.0], rng.standard_normal(4), np.full(4, 0.1)])
+    p = torch.tensor(pk, dtype=torch.float64, device=dev)
+    it = sode.Integrator("kuramoto", 4, 4, 9, precision=64, kernel="plain", shared_params=1)
+    builtin = timed(it, X0, p, 1e-3, nsteps, nsteps)
+    it.close()
+    emit("source_text", "kuramoto_n4_builtin", 64, "em", orbits, nsteps, builtin)
+    it = sode.Integrator.custom(NEXT_KURAMOTO4_DRIFT, NEXT_KURAMOTO4_DIFFUSION, 4, 4, 9, precision=64,
+                                shared_params=1)
+    t0 = time.perf_counter()
+    it.build()
+    build_s = time.perf_counter() - t0
+    ms = timed(it, X0, p, 1e-3, nsteps, nsteps)
+    it.close()
+    emit("source_text", "kuramoto_n4_text", 64, "em", orbits, nsteps, ms, build_s=build_s,
+         over_builtin=ms / builtin)
+
+
 PAPER_N = (5, 10, 15)
 PAPER_M = (512, 5120, 25600, 40960, 81920, 163840)
 
@@ -319,6 +405,9 @@ def parse():
                     help="instead of the benchmark line, run the Sec. 2.3.1 accuracy study "
                          "with this many realisations per (K, dt), oracle alongside")
     ap.add_argument("--oracle-threads", type=int, default=16)
+    ap.add_argument("--next-rows", action="store_true",
+                    help="time the Milstein, implicit and source-text model paths (one JSON "
+                         "line per case)")
     ap.add_argument("--rnn-only", choices=("bf16", "bf16x3", "fp32"), default=None,
                     help="time only the dense-network workload with this matrix variant "
                          "(one warm-up and one timed launch) and print its JSON")
@@ -349,6 +438,9 @@ def main():
         return
     if args.accuracy_study:
         accuracy_study(sode, torch, workloads, dev, args.accuracy_study, args.oracle_threads)
+        return
+    if args.next_rows:
+        next_rows(sode, torch, dev)
         return
     if args.rnn_only:
         print(json.dumps(rnn_leg(sode, torch, workloads, dev, gemms=(args.rnn_only,))))

@@ -1,0 +1,9 @@
+// implicit_fixed_f64_euler.hip - the fixed-size implicit Euler kernels in binary64
+// (implicit_fixed.hpp), one translation unit per precision and method.
+#include "implicit_fixed.hpp"
+
+namespace sode {
+
+bool launch_implicit_fixed_f64_euler(const Request& r, hipError_t* e) { return launch_implicit_fixed<double, kImplicitEuler>(r, e); }
+
+}  // namespace sode

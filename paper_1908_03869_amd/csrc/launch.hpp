@@ -50,6 +50,12 @@ hipError_t launch_plain_f32(const Request& r);
 // Implicit Euler / implicit midpoint on the ODE limit, n <= kImplicitMaxN
 // (plain_implicit.hip; reached through the two launchers above).
 hipError_t launch_plain_implicit_f64(const Request& r);
+// Fixed-size implicit kernels (n = 1, 2, 3, 4, 6, 8): true if one took the
+// request, its launch status in *e.
+bool launch_implicit_fixed_f64_euler(const Request& r, hipError_t* e);
+bool launch_implicit_fixed_f64_midpoint(const Request& r, hipError_t* e);
+bool launch_implicit_fixed_f32_euler(const Request& r, hipError_t* e);
+bool launch_implicit_fixed_f32_midpoint(const Request& r, hipError_t* e);
 hipError_t launch_plain_implicit_f32(const Request& r);
 
 // Kuramoto, binary32, Euler-Maruyama: 16 lanes per orbit, any n <= 128

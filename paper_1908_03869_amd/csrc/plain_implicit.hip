@@ -34,6 +34,16 @@ hipError_t launch_implicit(const Request& r)
 {
     if (r.n > kImplicitMaxN)
         return hipErrorInvalidValue;
+    // Small systems: the fixed-size kernels (registers instead of private
+    // memory, the same results bit for bit).
+    hipError_t e = hipSuccess;
+    const bool euler = r.method == kImplicitEuler;
+    const bool fixed = sizeof(R) == 8 ? (euler ? launch_implicit_fixed_f64_euler(r, &e)
+                                               : launch_implicit_fixed_f64_midpoint(r, &e))
+                                      : (euler ? launch_implicit_fixed_f32_euler(r, &e)
+                                               : launch_implicit_fixed_f32_midpoint(r, &e));
+    if (fixed)
+        return e;
     switch (r.model) {
     case kKuramoto:
         return r.drift == 1 ? launch_model<KuramotoMeanField, R>(r) : launch_model<Kuramoto, R>(r);

@@ -72,18 +72,28 @@ __device__ __forceinline__ void solve_dense(int n, R* A, R* b)
 {
     for (int col = 0; col < n; ++col) {
         int piv = col;
-        for (int r = col + 1; r < n; ++r)
-            if (dev_fabs(A[r * C + col]) > dev_fabs(A[piv * C + col]))
+        R best = dev_fabs(A[col * C + col]);
+        for (int r = col + 1; r < n; ++r) {
+            const R v = dev_fabs(A[r * C + col]);
+            if (v > best) {
+                best = v;
                 piv = r;
-        if (piv != col) {
-            for (int c = 0; c < n; ++c) {
-                const R tmp = A[col * C + c];
-                A[col * C + c] = A[piv * C + c];
-                A[piv * C + c] = tmp;
             }
-            const R tb = b[col];
-            b[col] = b[piv];
-            b[piv] = tb;
+        }
+        // Swap rows col and piv.  Written as a pass over the candidate rows so
+        // that every index is known once the loops unroll (a fixed n keeps A
+        // in registers); the rows exchanged are the same.
+        for (int r = col + 1; r < n; ++r) {
+            if (r == piv) {
+                for (int c = 0; c < n; ++c) {
+                    const R tmp = A[col * C + c];
+                    A[col * C + c] = A[r * C + c];
+                    A[r * C + c] = tmp;
+                }
+                const R tb = b[col];
+                b[col] = b[r];
+                b[r] = tb;
+            }
         }
         for (int r = col + 1; r < n; ++r) {
             const R l = A[r * C + col] / A[col * C + col];
