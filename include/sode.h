@@ -203,8 +203,10 @@ int sode_get_option(sode_t h, const char* key, int64_t* value);
  *   out  [orbits][nsave][q]     nsave = nsteps/stride + 1; out[o][s] is the
  *                               observable of X^{s*stride}, so out[o][0] is
  *                               the observable of X0.  Kuramoto phases are
- *                               returned wrapped to [-pi, pi) by the FP32
- *                               coupled kernel and unwrapped otherwise.
+ *                               returned wrapped to [-pi, pi] by the
+ *                               coupled kernels (both precisions; the
+ *                               checkpoints of sode_forward_ckpt too) and
+ *                               unwrapped by the plain kernel.
  *   nsteps >= 0, stride >= 1, nsteps % stride == 0, else SODE_EINVAL.
  *   seed  key of the Philox-4x32-10 noise stream (Sec. 2.1.2 names the
  *         Random123 family).  Normal j of orbit o at step k comes from the
