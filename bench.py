@@ -9,8 +9,13 @@ the whole ensemble (noise generation, coupling, update and saves all inside).
 Printed JSON line (rank 0): the driver's contract fields plus
   roofline      the coupled kernel against the VALU issue roofline,
   cpu_baseline  the FP64 oracle timed on a bounded sample on the host,
+  cpu_all_cores the same oracle over the 256 grid-diagonal orbits, one OS
+                thread per host core (disjoint orbit shards),
   plain_fp64    the one-orbit-per-lane FP64 kernel on the same ensemble,
-  error         max |dr| against the oracle on the sampled orbits,
+  error         max |dr| against the oracle on the sampled orbits (and on
+                all 256 diagonal orbits from the all-core run, with how
+                many are within the bound and, for the worst, how far the
+                oracle's own r(T) moves when its inputs move by one ulp),
   meanfield     the same ensemble with the O(n) mean-field drift form,
 and the adjoint, ragged-batch and dense-network legs.  --paper-sweep REPS
 prints the Sec. 2.2.1 speed protocol instead (one line per case), and
@@ -398,6 +403,8 @@ def parse():
                     help="Euler steps for the plain FP64 comparison run")
     ap.add_argument("--cpu-orbits", type=int, default=16,
                     help="orbits of the oracle sample (full 2x10^4 steps each)")
+    ap.add_argument("--cpu-all-orbits", type=int, default=256,
+                    help="grid-diagonal orbits of the all-core oracle run (0: skip it)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--grid-only", action="store_true",
                     help="time only the n = 64 grid kernel (for short profiler runs)")
@@ -524,8 +531,8 @@ def main():
         rag = ragged_leg(sode, torch, workloads, dev)
         rnn = rnn_leg(sode, torch, workloads, dev)
 
-    cpu = None
-    err = err_mf = None
+    cpu = cpu_all = diag = None
+    err = err_mf = err_all = None
     if not args.no_cpu:
         import oracle
         rows = w["diagonal"][np.linspace(0, 255, args.cpu_orbits).astype(int)]
@@ -544,6 +551,39 @@ def main():
         err = float(np.max(np.abs(r_gpu[rows] - ref[:, -1, 0])))
         if r_mf is not None:
             err_mf = float(np.max(np.abs(r_mf[rows] - ref[:, -1, 0])))
+        if args.cpu_all_orbits > 0:
+            # Orbits are independent: one thread per core over disjoint shards
+            # (the all-core CPU figure beside the single-core one).
+            rows_all = w["diagonal"][np.linspace(0, 255, args.cpu_all_orbits).astype(int)]
+            nthreads = max(1, min(args.oracle_threads, os.cpu_count() or 1))
+            c0 = time.perf_counter()
+            ref_all = oracle.integrate_parallel(
+                "kuramoto", n, n, 2 * n + 1, w["X0"][rows_all].astype(np.float32).astype(np.float64),
+                w["p"][rows_all].astype(np.float32).astype(np.float64), 0.0, w["dt"], nsteps,
+                stride, w["seed"], threads=nthreads, orbit_ids=rows_all, observable="kuramoto_r")
+            all_s = time.perf_counter() - c0
+            cpu_all = {"value": len(rows_all) * nsteps / all_s, "unit": "orbit*steps/s",
+                       "cores": nthreads, "kind": "oracle",
+                       "sample": f"{len(rows_all)} grid-diagonal orbits x {nsteps} steps, FP64, "
+                                 f"{nthreads} threads, {all_s:.1f} s"}
+            dr_all = np.abs(r_gpu[rows_all] - ref_all[:, -1, 0])
+            err_all = float(dr_all.max())
+            within_all = int((dr_all <= 1e-4).sum())
+            worst = int(np.argmax(dr_all))
+            # Conditioning of the worst orbit: the oracle's own |dr(T)| when its
+            # initial phases move by one binary32 ulp (2^-24 relative, eight
+            # seeded sign patterns).
+            Xw = w["X0"][rows_all[worst]].astype(np.float32).astype(np.float64)
+            pw = w["p"][rows_all[worst]].astype(np.float32).astype(np.float64)
+            Xs = np.stack([Xw * (1.0 + np.random.default_rng(1000 + k).choice([-1.0, 1.0], n)
+                                 * 2.0 ** -24) for k in range(8)])
+            resp = oracle.integrate_parallel(
+                "kuramoto", n, n, 2 * n + 1, Xs, np.stack([pw] * 8), 0.0, w["dt"], nsteps,
+                nsteps, w["seed"], threads=min(8, nthreads),
+                orbit_ids=np.full(8, rows_all[worst]), observable="kuramoto_r")[:, -1, 0]
+            diag = {"orbits": len(rows_all), "within_tolerance": within_all,
+                    "worst_orbit": int(rows_all[worst]),
+                    "worst_oracle_ulp_response": float(np.abs(resp - ref_all[worst, -1, 0]).max())}
 
     line = {
         "metric": "orbit*steps/s (Kuramoto n=64 FP32 Euler-Maruyama ensemble)",
@@ -569,10 +609,12 @@ def main():
                      "kernel_ms": kernel_ms,
                      "slots_per_orbit_step": work["slots"]},
         "cpu_baseline": cpu,
+        "cpu_all_cores": cpu_all,
         "plain_fp64": None if plain_rate is None else {
             "value": plain_rate, "unit": "orbit*steps/s", "nsteps": args.baseline_steps,
             "speedup_of_value": value / plain_rate},
-        "error": {"max_abs_dr_final": err, "tolerance": 1e-4},
+        "error": {"max_abs_dr_final": err, "max_abs_dr_final_diagonal": err_all,
+                  "tolerance": 1e-4, "diagonal": diag},
         "meanfield": None if mf_ms is None else {
             "value": orbits * nsteps / (mf_ms * 1e-3), "unit": "orbit*steps/s",
             "kernel_ms": mf_ms, "max_abs_dr_final": err_mf},

@@ -133,23 +133,67 @@ def test_coupled_fp32_order_parameter(gpu):
     assert err.max() <= 1e-4, err.max()
 
 
-def test_kuramoto_grid_full_size_sampled(gpu):
+def _oracle_ulp_response(w, rows, ref, samples=8):
+    """How far the FP64 oracle's own r moves when each initial phase of the
+    (binary32-rounded) input is changed by one binary32 ulp in relative
+    terms, 2^-24, with seeded random signs: the largest |dr| over `samples`
+    such perturbations, per orbit and save."""
+    import oracle
+    from gpu_util import as_received, threads
+    X = as_received(w["X0"][rows], 32)
+    p = as_received(w["p"][rows], 32)
+    Xs, ids = [], []
+    for k in range(samples):
+        sign = np.random.default_rng(1000 + k).choice([-1.0, 1.0], X.shape)
+        Xs.append(X * (1.0 + sign * 2.0 ** -24))
+        ids.append(rows)
+    n = w["n"]
+    r = oracle.integrate_parallel("kuramoto", n, n, 2 * n + 1, np.concatenate(Xs),
+                                  np.concatenate([p] * samples), 0.0, w["dt"], w["nsteps"],
+                                  w["stride"], w["seed"], threads=threads(),
+                                  orbit_ids=np.concatenate(ids), observable="kuramoto_r")
+    r = r.reshape(samples, len(rows), -1)
+    return np.abs(r - ref[None, :, :, 0]).max(axis=0)
+
+
+def test_kuramoto_grid_full_size_diagonal(gpu):
     """The full n = 64 workload (65,536 orbits, 2x10^4 steps, r every 100
-    steps) in the launch configuration the benchmark times; 24 orbits of
-    the grid diagonal checked against the oracle: |dr| <= 1e-4 at the final
-    time, the workload's stated bound.  Intermediate saves are held to 1e-3:
-    near the synchronisation transition the ensemble is briefly sensitive
-    and binary32 rounding differences grow before they decay again."""
+    steps) in the launch configuration the benchmark times, checked against
+    the oracle on all 256 orbits of the K-sigma grid diagonal: |dr| <= 1e-4
+    at the final time (the workload's stated bound) and <= 1e-3 at the
+    intermediate saves.
+
+    Near the synchronisation transition some orbits are chaotic: there the
+    oracle itself, started from inputs one binary32 ulp away, moves r by
+    more than these bounds, so no computation from binary32 inputs can meet
+    them.  An orbit over a bound must therefore be shown ill-conditioned:
+    over eight seeded one-ulp perturbations of its initial phases the
+    oracle's own |dr| reaches at least a tenth of that bound.  Such an orbit
+    is held to ten times the bound instead, and at most 4 of the 256 may
+    take this exception."""
     w = workloads.kuramoto_grid()
     log("kuramoto_grid full size fp32 coupled")
     got = run_library(w, precision=32)
     assert got.shape == (65536, 201, 1)
     assert np.all(np.isfinite(got)) and got.min() >= 0.0 and got.max() <= 1.0 + 1e-6
-    rows = w["diagonal"][::11]
+    rows = w["diagonal"]
     want = run_oracle(w, rows=rows, precision=32)
-    err = np.abs(got[rows] - want)
-    assert err[:, -1].max() <= 1e-4, err[:, -1].max()
-    assert err.max() <= 1e-3, err.max()
+    err = np.abs(got[rows] - want)[:, :, 0]
+    final_over = err[:, -1] > 1e-4
+    mid_over = err[:, :-1].max(axis=1) > 1e-3
+    over = np.where(final_over | mid_over)[0]
+    print(f"within bounds: {256 - len(over)} of 256; max |dr(T)| {err[:, -1].max():.2e}")
+    assert len(over) <= 4, over
+    if len(over):
+        resp = _oracle_ulp_response(w, rows[over], want[over])
+        for j, i in enumerate(over):
+            print(f"orbit {rows[i]}: |dr(T)| {err[i, -1]:.2e} (oracle one-ulp response "
+                  f"{resp[j, -1]:.2e}), max |dr| before T {err[i, :-1].max():.2e} "
+                  f"(response {resp[j, :-1].max():.2e})")
+            if final_over[i]:
+                assert resp[j, -1] >= 1e-5 and err[i, -1] <= 1e-3
+            if mid_over[i]:
+                assert resp[j, :-1].max() >= 1e-4 and err[i, :-1].max() <= 1e-2
 
 
 # --------------------------------------------------------------------------- addressing
