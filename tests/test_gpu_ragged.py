@@ -1,5 +1,5 @@
 """Ragged FitzHugh-Nagumo batches in one persistent launch, against the FP64
-oracle (64 stratified instances of the 4096-instance workload) and against
+oracle (every instance of the 4096-instance workload) and against
 itself under every schedule: persistent or direct, graph replay or eager,
 every lane shape and grid size give bitwise the same result.
 
@@ -46,32 +46,64 @@ def _oracle_instance(args):
                             orbit_ids=[oid])[0]
 
 
-def test_full_workload_matches_oracle_on_stratified_instances(gpu):
+def _oracle_ulp_response(args, samples=8):
+    """Largest relative change of the oracle's own result over `samples`
+    seeded perturbations of the instance's initial state by one binary32
+    ulp in relative terms (2^-24, random signs)."""
+    X0, p, n, nsteps, stride, seed, oid = args
+    ref = _oracle_instance(args)
+    scale = max(1.0, np.abs(ref).max())
+    worst = 0.0
+    for k in range(samples):
+        sign = np.random.default_rng(1000 + k).choice([-1.0, 1.0], X0.shape)
+        r = _oracle_instance((X0 * (1.0 + sign * 2.0 ** -24), p, n, nsteps, stride, seed, oid))
+        worst = max(worst, np.abs(r - ref).max() / scale)
+    return worst
+
+
+def test_full_workload_matches_oracle_on_every_instance(gpu):
+    """All 4096 instances of the workload (2.59e9 unit-steps; the oracle
+    takes ~36 ns per unit-step, ~7 s on 16 host threads) in the autotuned,
+    graph-captured launch the benchmark times.
+
+    Over tens of thousands of steps the noise-driven spikes of some chains
+    make them ill-conditioned: the oracle itself, started from a state one
+    binary32 ulp away, moves by more than the bound.  An instance over the
+    bound must be shown to be such a case (its oracle one-ulp response,
+    over eight seeded perturbations, reaches a tenth of the bound); it is
+    then held to ten times the bound, and at most 1 % of the instances may
+    take this route."""
     from concurrent.futures import ThreadPoolExecutor
     w = workloads.fhn_ragged()
     idx, b, X0, p = _batch(w)
     log("ragged fhn full workload (autotuned, graph)")
     out, cfg = _run(b, X0, p, w["dt"])
     print(f"autotuned waves/CU, units/lane: {cfg}")
-    cost = w["units"] * w["nsteps"]
-    order = np.argsort(cost, kind="stable")
-    picks = order[np.linspace(0, len(order) - 1, 64).astype(int)]
+    # Largest instances first, so the pool's tail is short.
+    order = np.argsort(-(w["units"] * w["nsteps"]), kind="stable")
     X0r, pr = as_received(X0, 32), as_received(p, 32)
     args = []
-    for i in picks:
+    for i in order:
         a = int(b.x0_offset[i])
         n = int(b.n[i])
         args.append((X0r[a:a + n], pr[5 * i:5 * i + 5], n, int(b.nsteps[i]), int(b.stride[i]),
                      w["seed"], int(i)))
     with ThreadPoolExecutor(max_workers=threads()) as ex:
         refs = list(ex.map(_oracle_instance, args))
-    worst = 0.0
-    for i, ref in zip(picks, refs):
+    err = np.empty(len(order))
+    for j, (i, ref) in enumerate(zip(order, refs)):
         got = b.unpack(out, int(i))
-        err = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
-        worst = max(worst, err)
-    print(f"worst relative error over 64 stratified instances: {worst:.2e}")
-    assert worst <= 1e-4
+        err[j] = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
+    over = np.where(err > 1e-4)[0]
+    print(f"within 1e-4: {len(order) - len(over)} of {len(order)}; worst {err.max():.2e}")
+    assert len(over) <= len(order) // 100, over
+    with ThreadPoolExecutor(max_workers=threads()) as ex:
+        resp = list(ex.map(_oracle_ulp_response, [args[j] for j in over]))
+    for j, r in zip(over, resp):
+        i = order[j]
+        print(f"instance {i}: {w['units'][i]} units x {w['nsteps'][i]} steps, relative error "
+              f"{err[j]:.2e}, oracle one-ulp response {r:.2e}")
+        assert r >= 1e-5 and err[j] <= 1e-3
 
 
 def test_schedules_and_shapes_are_bitwise_identical(gpu):
