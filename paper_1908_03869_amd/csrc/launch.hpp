@@ -47,6 +47,10 @@ PlainArgs<R> plain_args(const Request& r);
 // one work-item per orbit).  Returns a hipError_t.
 hipError_t launch_plain_f64(const Request& r);
 hipError_t launch_plain_f32(const Request& r);
+// Explicit steppers with a compile-time state size (plain_fixed.hip): true if
+// one exists for the request's model and n (its launch status in *e).
+bool launch_plain_fixed_f64(const Request& r, hipError_t* e);
+bool launch_plain_fixed_f32(const Request& r, hipError_t* e);
 // Implicit Euler / implicit midpoint on the ODE limit, n <= kImplicitMaxN
 // (plain_implicit.hip; reached through the two launchers above).
 hipError_t launch_plain_implicit_f64(const Request& r);

@@ -66,6 +66,17 @@ hipError_t launch_one(const Request& r)
     return hipGetLastError();
 }
 
+// The fixed-size kernel of plain_fixed.hip where there is one for r.n, else
+// the runtime-n kernel.
+template <class Model, typename R>
+hipError_t launch_fixed_or(const Request& r)
+{
+    hipError_t e = hipSuccess;
+    if (sizeof(R) == 8 ? launch_plain_fixed_f64(r, &e) : launch_plain_fixed_f32(r, &e))
+        return e;
+    return launch_one<Model, R, 0>(r);
+}
+
 template <typename R>
 hipError_t launch_plain(const Request& r)
 {
@@ -92,13 +103,13 @@ hipError_t launch_plain(const Request& r)
     case kOU:
         if (r.n == 1)
             return launch_one<OrnsteinUhlenbeck, R, 1>(r);
-        return launch_one<OrnsteinUhlenbeck, R, 0>(r);
+        return launch_fixed_or<OrnsteinUhlenbeck, R>(r);
     case kGBM:
         if (r.n == 1)
             return launch_one<GeometricBM, R, 1>(r);
-        return launch_one<GeometricBM, R, 0>(r);
+        return launch_fixed_or<GeometricBM, R>(r);
     case kFHN:
-        return launch_one<FhnChain, R, 0>(r);
+        return launch_fixed_or<FhnChain, R>(r);
     case kRNN:
         return launch_one<DenseRnn, R, 0>(r);
     default:

@@ -56,6 +56,38 @@ def test_plain_models_fp64(gpu, model, n, m, d, p, x0):
     assert np.max(np.abs(got - want) / scale) <= 1e-10
 
 
+FHN_P = [0.7, 0.8, 0.08, 0.1, 0.05]
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("method", ["em", "milstein", "rk4"])
+@pytest.mark.parametrize("model,n,m,d,p,x0", [
+    ("ou", 2, 2, 3, [0.5, -1.0, 0.8], 0.3),
+    ("ou", 3, 3, 3, [1.5, 0.2, 0.4], 1.0),
+    ("gbm", 2, 2, 2, [0.3, 0.5], 1.0),
+    ("gbm", 4, 4, 2, [-0.2, 0.3], 2.0),
+    ("fhn", 2, 1, 5, FHN_P, -1.0),
+    ("fhn", 4, 2, 5, FHN_P, -1.0),
+    ("fhn", 6, 3, 5, FHN_P, -1.0),
+    ("fhn", 10, 5, 5, FHN_P, -1.0),
+])
+def test_plain_small_systems(gpu, model, n, m, d, p, x0, method, precision):
+    """The explicit steppers with a compile-time state size (OU and GBM
+    n = 2..4, FHN n = 2..8) and one runtime-n neighbour (FHN n = 10), in
+    both precisions, against the oracle: relative 1e-10 in binary64 and
+    1e-4 in binary32 (400 uncompensated steps, |X| ~ 1)."""
+    rng = np.random.default_rng(n * 17 + d)
+    orbits = 77
+    X0 = x0 + 0.1 * rng.standard_normal((orbits, n))
+    w = dict(model=model, n=n, m=m, d=d, X0=X0, p=np.asarray(p, float), t0=0.0, dt=1e-2,
+             nsteps=400, stride=40, seed=123)
+    log(f"plain small {model} n={n} {method} fp{precision}")
+    got = run_library(w, precision=precision, kernel="plain", method=method)
+    want = run_oracle(w, method=method, precision=precision)
+    scale = np.maximum(1.0, np.abs(want))
+    assert np.max(np.abs(got - want) / scale) <= (1e-10 if precision == 64 else 1e-4)
+
+
 def test_plain_fp32_ou(gpu):
     rng = np.random.default_rng(4)
     w = dict(model="ou", n=4, m=4, d=3, X0=rng.standard_normal((130, 4)),
