@@ -80,20 +80,21 @@ __device__ __forceinline__ void solve_dense(int n, R* A, R* b)
                 piv = r;
             }
         }
-        // Swap rows col and piv.  Written as a pass over the candidate rows so
-        // that every index is known once the loops unroll (a fixed n keeps A
-        // in registers); the rows exchanged are the same.
+        // Swap rows col and piv.  Written as a pass over the candidate rows
+        // that selects values, with every load and store unconditional, so
+        // that every index is known once the loops unroll and no address
+        // depends on the pivot (a fixed n keeps A in registers); the rows
+        // exchanged are the same.
         for (int r = col + 1; r < n; ++r) {
-            if (r == piv) {
-                for (int c = 0; c < n; ++c) {
-                    const R tmp = A[col * C + c];
-                    A[col * C + c] = A[r * C + c];
-                    A[r * C + c] = tmp;
-                }
-                const R tb = b[col];
-                b[col] = b[r];
-                b[r] = tb;
+            const bool sw = r == piv;
+            for (int c = 0; c < n; ++c) {
+                const R top = A[col * C + c], row = A[r * C + c];
+                A[col * C + c] = sw ? row : top;
+                A[r * C + c] = sw ? top : row;
             }
+            const R tb = b[col], rb = b[r];
+            b[col] = sw ? rb : tb;
+            b[r] = sw ? tb : rb;
         }
         for (int r = col + 1; r < n; ++r) {
             const R l = A[r * C + col] / A[col * C + col];
