@@ -62,9 +62,9 @@ def algorithmic_slots_per_orbit_step(n: int, compensated: bool = True) -> dict:
         # per pair: one difference, one sine, two accumulations
         "valu": pairs * 3
         # per oscillator: scale to revolutions, two FMAs for the increment,
-        # the state update (a six-op two-sum when compensated, else one
+        # the state update (a four-op Fast2Sum when compensated, else one
         # add) and the 2 pi wrap (scale, round, two FMAs)
-        + n * (3 + (6 if compensated else 1) + 4)
+        + n * (3 + (4 if compensated else 1) + 4)
         # per Box-Muller pair: two int->float conversions, two scalings,
         # one radius scaling, two products
         + bm_pairs * 7

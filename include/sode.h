@@ -184,7 +184,8 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *   "compensated"  binary32 Kuramoto kernels (coupled, forward_ckpt,
  *                  adjoint) and the ragged FHN kernel: 1 (default) carries
  *                  each state variable as hi + lo and adds every increment
- *                  with an error-free two-sum, so rounding no longer
+ *                  with Dekker's Fast2Sum (exact while |hi| is at least the
+ *                  increment, i.e. away from zero), so rounding no longer
  *                  accumulates over the steps (saved states hold hi;
  *                  resuming from them restarts lo at 0); 0 keeps a single
  *                  binary32 value (saved states resume bit-exactly).

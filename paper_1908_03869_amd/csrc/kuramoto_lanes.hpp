@@ -225,8 +225,8 @@ __device__ __forceinline__ void mean_field_sums(const float (&phi)[P], float (&a
 // One Euler-Maruyama step (Eq. 6) of the lane's P oscillators at global
 // step k: theta += omega dt + (K/N) S dt + p sqrt(dt) xi, then wrap.
 // COMP: th is the leading part of hi + lo and tl the trailing part; the
-// increment and the old trailing part are added with an error-free two-sum,
-// and a wrap moves the tail of 2 pi into tl.  MF: coupling through the
+// increment and the old trailing part are added with a compensated sum
+// (Fast2Sum), and a wrap moves the tail of 2 pi into tl.  MF: coupling through the
 // mean-field identity instead of pairwise sines.  PAD: see the top of the file.
 // xi_out (optional) receives the step's P normals; xi_in (optional) supplies
 // them, already drawn (lane_normals_steps), instead of lane_normals.
@@ -266,10 +266,13 @@ __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const La
         const float kc = PAD ? c.kc[i] : c.kc[0];
         const float inc = __builtin_fmaf(c.noise_scale[i], xi[i], __builtin_fmaf(kc, acc[i], c.drift0[i]));
         if constexpr (COMP) {
+            // Dekker's Fast2Sum of th and y: exact when |th| >= |y|.  Phases
+            // are O(1) and increments O(dt), so that holds except within a
+            // few increments of zero, where what it may leave out is below
+            // an ulp of a sum that small.
             const float y = inc + tl[i];
             const float s = th[i] + y;
-            const float yv = s - th[i];
-            const float err = (th[i] - (s - yv)) + (y - yv);
+            const float err = y - (s - th[i]);
             const float kw = __builtin_rintf(s * kInvTwoPi);
             th[i] = __builtin_fmaf(-kw, kTwoPiHead, s);
             tl[i] = __builtin_fmaf(-kw, kTwoPiTail, err);
