@@ -5,8 +5,8 @@
 // paper measured in (Sec. 2.2.1): lane l of a 16-lane DPP row owns the
 // P = ceil(N/16) oscillators P*l .. P*l+P-1 (rows of N < 16P padded with
 // oscillators frozen at phase 0 whose terms are cancelled, as in the binary32
-// kernel); every unordered pair {i, j} is evaluated once with the correctly
-// rounded binary64 sine and used for both oscillators; 64-bit values cross
+// kernel); every unordered pair {i, j} is evaluated once with the device
+// library's binary64 sine and used for both oscillators; 64-bit values cross
 // lanes as two 32-bit DPP row rotations.  The state is kept in radians and
 // wrapped to [-pi, pi] every step (theta - k 2pi_hi - k 2pi_lo, no rounding
 // when k = 0).  Normals are the binary64 Box-Muller pairs of the plain

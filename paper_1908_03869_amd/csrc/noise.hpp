@@ -71,7 +71,7 @@ __device__ __forceinline__ void box_muller_f32(uint32_t a, uint32_t b, float& z_
     z_sin = radius * __builtin_amdgcn_sinf(u2);
 }
 
-// Binary64 version on the correctly rounded library functions; sincospi
+// Binary64 version on the device math library's functions; sincospi
 // takes the half-turn count 2 U2 and avoids rounding 2 pi U2 first.
 __device__ __forceinline__ void box_muller_f64(uint32_t a, uint32_t b, double& z_cos, double& z_sin)
 {
