@@ -113,6 +113,28 @@ def adjoint_leg(sode, torch, workloads, dev, reps: int = 3) -> dict:
             "grad_norm": float(grad.norm())}
 
 
+def ragged_alone_ms(sode, torch, w, j: int, cfg, dev) -> float:
+    """Instance j of the ragged workload run alone, in a batch of one, with
+    the shape parameters cfg = (waves per CU, units per lane): one warm-up
+    and one timed call (HIP events on the launch stream), in ms."""
+    stream = torch.cuda.current_stream()
+    b1 = sode.RaggedBatch([2 * w["units"][j]], [w["nsteps"][j]], w["stride"], w["seed"], [j], d=5)
+    X1 = torch.tensor(b1.pack([w["X0"][j]]), dtype=torch.float32, device=dev)
+    p1 = torch.tensor(b1.pack([w["params"][j]]), dtype=torch.float32, device=dev)
+    it1 = sode.Integrator("fhn", 256, 128, 5, precision=32, waves_per_cu=cfg[0],
+                          units_per_lane=cfg[1])
+    it1.integrate_ragged(b1, X1, p1, 0.0, w["dt"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    it1.integrate_ragged(b1, X1, p1, 0.0, w["dt"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1)
+    it1.close()
+    return t
+
+
 def ragged_leg(sode, torch, workloads, dev, reps: int = 5) -> dict:
     """Makespan of the 4096-instance FitzHugh-Nagumo batch in one persistent,
     graph-captured launch (autotuned on the first, untimed call), and the
@@ -147,20 +169,7 @@ def ragged_leg(sode, torch, workloads, dev, reps: int = 5) -> dict:
     by_work = np.argsort(-(w["units"] * w["nsteps"]), kind="stable")[:4]
     alone, jc = -1.0, int(by_work[0])
     for j in dict.fromkeys(int(c) for c in list(by_steps) + list(by_work)):
-        b1 = sode.RaggedBatch([2 * w["units"][j]], [w["nsteps"][j]], w["stride"], w["seed"], [j], d=5)
-        X1 = torch.tensor(b1.pack([w["X0"][j]]), dtype=torch.float32, device=dev)
-        p1 = torch.tensor(b1.pack([w["params"][j]]), dtype=torch.float32, device=dev)
-        it1 = sode.Integrator("fhn", 256, 128, 5, precision=32, waves_per_cu=cfg[0],
-                              units_per_lane=cfg[1])
-        it1.integrate_ragged(b1, X1, p1, 0.0, w["dt"])
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        it1.integrate_ragged(b1, X1, p1, 0.0, w["dt"])
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1)
-        it1.close()
+        t = ragged_alone_ms(sode, torch, w, j, cfg, dev)
         if t > alone:
             alone, jc = t, j
     return {"workload": "fhn_ragged_4096", "instances": b.count, "unit_steps": unit_steps,
@@ -418,6 +427,13 @@ def parse():
     ap.add_argument("--rnn-only", choices=("bf16", "bf16x3", "fp32"), default=None,
                     help="time only the dense-network workload with this matrix variant "
                          "(one warm-up and one timed launch) and print its JSON")
+    ap.add_argument("--ragged-alone", type=int, default=None, metavar="INSTANCE",
+                    help="time one instance of the ragged FHN workload alone (a batch of one; "
+                         "one warm-up and one timed launch) and print its JSON")
+    ap.add_argument("--waves-per-cu", type=int, default=4,
+                    help="ragged shape for --ragged-alone: persistent waves per CU")
+    ap.add_argument("--units-per-lane", type=int, default=1,
+                    help="ragged shape for --ragged-alone: minimum units per lane")
     ap.add_argument("--paper-sweep", type=int, default=0, metavar="REPS",
                     help="instead of the benchmark line, time the Sec. 2.2.1 speed protocol "
                          "(N x M x precision x drift form), REPS runs per case")
@@ -451,6 +467,15 @@ def main():
         return
     if args.rnn_only:
         print(json.dumps(rnn_leg(sode, torch, workloads, dev, gemms=(args.rnn_only,))))
+        return
+    if args.ragged_alone is not None:
+        w = workloads.fhn_ragged()
+        j = args.ragged_alone
+        ms = ragged_alone_ms(sode, torch, w, j, (args.waves_per_cu, args.units_per_lane), dev)
+        print(json.dumps({"workload": "fhn_ragged_4096", "instance": j,
+                          "units": int(w["units"][j]), "nsteps": int(w["nsteps"][j]),
+                          "waves_per_cu": args.waves_per_cu, "units_per_lane": args.units_per_lane,
+                          "kernel_ms": ms, "ns_per_step": ms * 1e6 / int(w["nsteps"][j])}))
         return
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
