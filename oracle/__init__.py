@@ -28,16 +28,17 @@ OBSERVABLES = {"state": 0, "kuramoto_r": 1}
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with the flags its header fixes."""
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
+def build(force: bool = True, *, src: str = SRC, out: str = LIB) -> str:
+    """Compile the oracle with the flags its header fixes (``src`` and
+    ``out`` default to the oracle's own source and library)."""
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
              "-D_DEFAULT_SOURCE", "-Wall", "-Wextra", "-fPIC", "-shared",
-             "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+             "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 def lib():
@@ -45,45 +46,52 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build(force=True)
-        L = ctypes.CDLL(LIB)
-        u32p = ctypes.POINTER(ctypes.c_uint32)
-        u64p = ctypes.POINTER(ctypes.c_uint64)
-        f64p = ctypes.POINTER(ctypes.c_double)
-        L.oracle_philox.argtypes = [u32p, u32p, u32p]
-        L.oracle_philox.restype = None
-        L.oracle_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32, f64p]
-        L.oracle_box_muller.restype = None
-        L.oracle_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-                                     ctypes.c_int32, f64p]
-        L.oracle_normals.restype = None
-        L.oracle_model_dims_ok.argtypes = [ctypes.c_int32] * 4
-        L.oracle_model_dims_ok.restype = ctypes.c_int
-        L.oracle_drift.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_double, f64p, f64p, f64p]
-        L.oracle_drift.restype = None
-        L.oracle_diffusion.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_double, f64p, f64p,
-                                                               f64p, f64p]
-        L.oracle_diffusion.restype = None
-        L.oracle_order_parameter.argtypes = [ctypes.c_int32, f64p]
-        L.oracle_order_parameter.restype = ctypes.c_double
-        L.oracle_integrate.argtypes = (
-            [ctypes.c_int32] * 4
-            + [f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
-               ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
-               ctypes.c_uint64, u32p, u64p, ctypes.c_int32, ctypes.c_int32, f64p])
-        L.oracle_integrate.restype = ctypes.c_int
-        L.oracle_integrate_custom.argtypes = (
-            [ctypes.c_int32] * 3 + [ctypes.c_void_p, ctypes.c_void_p]
-            + [f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
-               ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
-               ctypes.c_uint64, u32p, u64p, ctypes.c_int32, f64p])
-        L.oracle_integrate_custom.restype = ctypes.c_int
-        L.oracle_kuramoto_adjoint.argtypes = [
-            ctypes.c_int32, f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
-            ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
-            ctypes.c_uint64, ctypes.c_uint64, f64p, f64p, f64p, f64p]
-        L.oracle_kuramoto_adjoint.restype = ctypes.c_int
-        _lib = L
+        _lib = bind(LIB)
     return _lib
+
+
+def bind(path: str):
+    """Load an oracle shared library from ``path`` and declare its entry
+    points.  ``lib()`` binds the built oracle; the pin tests also bind copies
+    compiled from deliberately altered source, to show that a pin fails."""
+    L = ctypes.CDLL(path)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    f64p = ctypes.POINTER(ctypes.c_double)
+    L.oracle_philox.argtypes = [u32p, u32p, u32p]
+    L.oracle_philox.restype = None
+    L.oracle_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32, f64p]
+    L.oracle_box_muller.restype = None
+    L.oracle_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                 ctypes.c_int32, f64p]
+    L.oracle_normals.restype = None
+    L.oracle_model_dims_ok.argtypes = [ctypes.c_int32] * 4
+    L.oracle_model_dims_ok.restype = ctypes.c_int
+    L.oracle_drift.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_double, f64p, f64p, f64p]
+    L.oracle_drift.restype = None
+    L.oracle_diffusion.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_double, f64p, f64p,
+                                                           f64p, f64p]
+    L.oracle_diffusion.restype = None
+    L.oracle_order_parameter.argtypes = [ctypes.c_int32, f64p]
+    L.oracle_order_parameter.restype = ctypes.c_double
+    L.oracle_integrate.argtypes = (
+        [ctypes.c_int32] * 4
+        + [f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+           ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
+           ctypes.c_uint64, u32p, u64p, ctypes.c_int32, ctypes.c_int32, f64p])
+    L.oracle_integrate.restype = ctypes.c_int
+    L.oracle_integrate_custom.argtypes = (
+        [ctypes.c_int32] * 3 + [ctypes.c_void_p, ctypes.c_void_p]
+        + [f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+           ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
+           ctypes.c_uint64, u32p, u64p, ctypes.c_int32, f64p])
+    L.oracle_integrate_custom.restype = ctypes.c_int
+    L.oracle_kuramoto_adjoint.argtypes = [
+        ctypes.c_int32, f64p, f64p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+        ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+        ctypes.c_uint64, ctypes.c_uint64, f64p, f64p, f64p, f64p]
+    L.oracle_kuramoto_adjoint.restype = ctypes.c_int
+    return L
 
 
 def _f64(a):

@@ -372,6 +372,102 @@ def test_fhn_laplacian_no_flux(oracle_lib):
     np.testing.assert_allclose((coup - base)[:N], lap, atol=1e-14)
 
 
+def _fhn_fixed_point(a, b):
+    """Resting state of one FitzHugh-Nagumo unit: the real root of
+    v^3 + 3 (1/b - 1) v + 3 a / b = 0, w = (v + a) / b (numpy's polynomial roots)."""
+    roots = np.roots([1.0, 0.0, 3 * (1 / b - 1), 3 * a / b])
+    v = float(roots[np.argmin(np.abs(roots.imag))].real)
+    return v, (v + a) / b
+
+
+def check_fhn_one_step_drift(oracle_lib):
+    """sigma = D = 0, one Euler-Maruyama step from states off the fixed point,
+    with a, b and eps all different from each other: the FitzHugh-Nagumo
+    equations dv = (v - v^3/3 - w) dt, dw = eps (v + a - b w) dt written out."""
+    a, b, eps, dt = 0.55, 1.3, 0.21, 0.01
+    v = np.array([0.4, -1.7, 1.1])
+    w = np.array([-0.3, 0.9, 0.25])
+    N = v.size
+    out = oracle_lib.integrate("fhn", 2 * N, N, 5, np.concatenate([v, w])[None],
+                               [a, b, eps, 0.0, 0.0], 0.0, dt, 1, 1, 7)
+    v1 = v + dt * (v - v ** 3 / 3 - w)
+    w1 = w + dt * (eps * (v + a - b * w))
+    np.testing.assert_allclose(out[0, 1, :N], v1, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(out[0, 1, N:], w1, rtol=0, atol=1e-14)
+
+
+def check_fhn_noise_on_v_only(oracle_lib):
+    """From the fixed point, with coupling on and sigma != eps: one step moves
+    each v_i by exactly sigma sqrt(dt) xi_i (xi_i the i-th normal of the
+    orbit's step-0 block) and leaves every w_i where it was."""
+    a, b, eps, D, sigma, dt, seed = 0.7, 0.8, 0.08, 0.1, 0.37, 0.01, 11
+    v, w = _fhn_fixed_point(a, b)
+    N = 4
+    X0 = np.concatenate([np.full(N, v), np.full(N, w)])[None]
+    out = oracle_lib.integrate("fhn", 2 * N, N, 5, X0, [a, b, eps, D, sigma], 0.0, dt, 1, 1, seed)
+    xi = oracle_lib.normals(seed, 0, 0, N)
+    np.testing.assert_allclose(out[0, 1, :N] - v, sigma * math.sqrt(dt) * xi, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(out[0, 1, N:], w, rtol=0, atol=1e-15)
+
+
+def check_fhn_linearisation(oracle_lib):
+    """sigma = D = 0: a perturbation delta of 1e-6 from the fixed point evolves,
+    to first order, as (I + dt J)^k delta with the Jacobian
+    J = [[1 - v*^2, -1], [eps, -eps b]] of the unit at (v*, w*) -- a stable
+    spiral for these parameters, so every entry of J shapes the result."""
+    a, b, eps, dt, k = 0.7, 0.8, 0.3, 0.01, 400
+    v, w = _fhn_fixed_point(a, b)
+    J = np.array([[1 - v * v, -1.0], [eps, -eps * b]])
+    A = np.linalg.matrix_power(np.eye(2) + dt * J, k)
+    for delta in (np.array([1e-6, 0.0]), np.array([0.0, 1e-6]), np.array([7e-7, -4e-7])):
+        X0 = np.array([[v + delta[0], w + delta[1]]])
+        out = oracle_lib.integrate("fhn", 2, 1, 5, X0, [a, b, eps, 0.0, 0.0], 0.0, dt, k, k, 3)
+        got = out[0, -1] - np.array([v, w])
+        want = A @ delta
+        assert np.linalg.norm(got - want) <= 1e-4 * np.linalg.norm(want), (got, want)
+
+
+FHN_CHECKS = (check_fhn_one_step_drift, check_fhn_noise_on_v_only, check_fhn_linearisation)
+
+
+@pytest.mark.parametrize("check", FHN_CHECKS, ids=lambda f: f.__name__[6:])
+def test_fhn_recovery_rate_and_noise(oracle_lib, check):
+    check(oracle_lib)
+
+
+# Mistakes a reading of the FHN parameter layout could make; each replaces
+# text of the oracle's source (every pattern occurs exactly once).
+FHN_MUTANTS = {
+    "recovery_rate_dropped": [("f[N + i] = eps * (v[i] + a - b * w[i]);",
+                               "f[N + i] = (v[i] + a - b * w[i]);")],
+    "eps_sigma_swapped": [("eps = p[2]", "eps = p[4]"),
+                          ("gx[i] = p[4] * xi[i];", "gx[i] = p[2] * xi[i];")],
+    "noise_on_w": [("gx[N + i] = 0.0;", "gx[N + i] = p[4] * xi[i];")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(FHN_MUTANTS))
+def test_fhn_pins_catch_planted_mistakes(oracle_lib, tmp_path, monkeypatch, name):
+    """Compile the oracle with one planted mistake and check that at least one
+    of the FHN pins above fails on it (the unaltered oracle passes them all)."""
+    with open(oracle_lib.SRC) as f:
+        src = f.read()
+    for old, new in FHN_MUTANTS[name]:
+        assert src.count(old) == 1, old
+        src = src.replace(old, new)
+    c_path = tmp_path / f"{name}.c"
+    c_path.write_text(src)
+    so = oracle_lib.build(force=True, src=str(c_path), out=str(tmp_path / f"{name}.so"))
+    monkeypatch.setattr(oracle_lib, "_lib", oracle_lib.bind(so))
+    failed = []
+    for check in FHN_CHECKS:
+        try:
+            check(oracle_lib)
+        except AssertionError:
+            failed.append(check.__name__)
+    assert failed, f"no FHN pin detects the mutant {name}"
+
+
 def test_rnn_drift_is_matmul(oracle_lib):
     """f = -X + W tanh X + b equals numpy's matrix product."""
     rng = np.random.default_rng(9)
