@@ -71,8 +71,8 @@ def test_full_workload_matches_oracle_on_every_instance(gpu):
     binary32 ulp away, moves by more than the bound.  An instance over the
     bound must be shown to be such a case (its oracle one-ulp response,
     over eight seeded perturbations, reaches a tenth of the bound); it is
-    then held to ten times the bound, and at most 1 % of the instances may
-    take this route."""
+    then held to twice that response instead of the bound, and at most 1 %
+    of the instances may take this route."""
     from concurrent.futures import ThreadPoolExecutor
     w = workloads.fhn_ragged()
     idx, b, X0, p = _batch(w)
@@ -103,7 +103,8 @@ def test_full_workload_matches_oracle_on_every_instance(gpu):
         i = order[j]
         print(f"instance {i}: {w['units'][i]} units x {w['nsteps'][i]} steps, relative error "
               f"{err[j]:.2e}, oracle one-ulp response {r:.2e}")
-        assert r >= 1e-5 and err[j] <= 1e-3
+        assert r >= 0.1 * 1e-4, "over the bound but well conditioned"
+        assert err[j] <= 2.0 * r, "more than twice the one-ulp response"
 
 
 def test_schedules_and_shapes_are_bitwise_identical(gpu):
