@@ -265,14 +265,16 @@ def next_rows(sode, torch, dev, reps: int = 3) -> None:
     X0 = torch.tensor(rng.uniform(-1.0, 1.0, (orbits, 6)), dtype=torch.float64, device=dev)
     p = torch.tensor([0.7, 0.8, 0.08, 0.1, 0.05], dtype=torch.float64, device=dev)
     for method in ("em", "rk4", "implicit_euler", "implicit_midpoint"):
-        it = sode.Integrator("fhn", 6, 3, 5, precision=64, method=method, kernel="plain", shared_params=1)
+        it = sode.Integrator("fhn", 6, 3, 5, precision=64, method=method, kernel="plain", shared_params=1,
+                             ode_limit=int(method != "em"))
         emit("implicit", "fhn_n6", 64, method, orbits, nsteps, timed(it, X0, p, 0.05, nsteps, nsteps))
         it.close()
     # Stiff OU (n = 3, a dt = 10): only the implicit steppers are stable.
     X0 = torch.tensor(rng.uniform(-1.0, 1.0, (orbits, 3)), dtype=torch.float64, device=dev)
     p = torch.tensor([1000.0, 0.3, 0.5], dtype=torch.float64, device=dev)
     for method in ("implicit_euler", "implicit_midpoint"):
-        it = sode.Integrator("ou", 3, 3, 3, precision=64, method=method, kernel="plain", shared_params=1)
+        it = sode.Integrator("ou", 3, 3, 3, precision=64, method=method, kernel="plain", shared_params=1,
+                             ode_limit=1)
         emit("implicit", "ou_stiff_n3", 64, method, orbits, nsteps, timed(it, X0, p, 0.01, nsteps, nsteps))
         it.close()
     # Source-text model vs the built-in one: Kuramoto n = 4, binary64.
@@ -293,6 +295,46 @@ def next_rows(sode, torch, dev, reps: int = 3) -> None:
     it.close()
     emit("source_text", "kuramoto_n4_text", 64, "em", orbits, nsteps, ms, build_s=build_s,
          over_builtin=ms / builtin)
+
+
+def op_rates(waves_per_simd=(1, 2, 4, 8)) -> None:
+    """Issue cost of each instruction class on gfx950, measured by the
+    op-rate microbenchmark (csrc/op_rates.hip, built as libop_rates.so): for
+    every class and W waves per SIMD (blocks of 4 waves, 256 W blocks), the
+    shader-clock cycles of each wave's loop give the SIMD cycles one wave64
+    instruction (or one library call) occupies, cycles / (instructions per
+    wave x W), and 64 lanes over that cost give lanes per clock per SIMD.
+    The effective clock is the mean cycle count over the launch duration.
+    One JSON line per (class, W)."""
+    import ctypes
+    from paper_1908_03869_amd import build as hipbuild
+
+    if not os.path.exists(hipbuild.OP_RATES_LIB):
+        raise RuntimeError(f"{hipbuild.OP_RATES_LIB} is missing: build the package first")
+    L = ctypes.CDLL(hipbuild.OP_RATES_LIB)
+    L.op_rates_count.restype = ctypes.c_int
+    L.op_rates_name.restype = ctypes.c_char_p
+    L.op_rates_name.argtypes = [ctypes.c_int]
+    L.op_rates_ops_per_wave.restype = ctypes.c_double
+    L.op_rates_ops_per_wave.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.op_rates_run.restype = ctypes.c_int
+    L.op_rates_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    for op in range(L.op_rates_count()):
+        name = L.op_rates_name(op).decode()
+        library = "library call" in name
+        iters = 100 if library else 4000
+        for W in waves_per_simd:
+            cyc, ms = ctypes.c_double(), ctypes.c_double()
+            rc = L.op_rates_run(op, 256 * W, 4, iters, ctypes.byref(cyc), ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"op_rates_run({name}) failed: {rc}")
+            ops = L.op_rates_ops_per_wave(op, iters)
+            cost = cyc.value / (ops * W)
+            print(json.dumps({"op_rates": name, "waves_per_simd": W, "iters": iters,
+                              "cycles_per_wave_op": cost, "lanes_per_clk_per_simd": 64.0 / cost,
+                              "clock_ghz": cyc.value / (ms.value * 1e6), "kernel_ms": ms.value}),
+                  flush=True)
 
 
 PAPER_N = (5, 10, 15)

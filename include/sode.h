@@ -137,7 +137,10 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *   "method"       0 = Euler-Maruyama, Eq. (2) of Sec. 2.1.1 (default);
  *                  1 = classical RK4 on the ODE limit g = 0 (Sec. 1.1; the
  *                      Runge-Kutta ODE solver of Sec. 1.5): the diffusion is
- *                      ignored and no noise is drawn;
+ *                      ignored and no noise is drawn.  Every built-in model
+ *                      has a diffusion, as has a source-text model with
+ *                      m > 0: for those, integrate returns
+ *                      SODE_EUNSUPPORTED unless "ode_limit" is 1;
  *                  2 = Milstein, the strong order-one scheme named as the
  *                      next stochastic method (Sec. 1.5, Sec. 4), for
  *                      diagonal noise: the EM increment plus
@@ -152,7 +155,20 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                      correction of 64 eps (1 + max|Y|); a step that has
  *                      not converged after 50 iterations sets the state to
  *                      NaN.  Plain kernel only, n <= 16 (each lane holds an
- *                      n x n matrix).
+ *                      n x n matrix); "ode_limit" as for RK4.
+ *   "ode_limit"    0 (default) = RK4 and the implicit methods are refused
+ *                  (SODE_EUNSUPPORTED) on a model with a diffusion;
+ *                  1 = they integrate its ODE limit g = 0.
+ *   "wrap"         Kuramoto phases (saved states and checkpoints):
+ *                  1 (default) = every kernel returns them reduced to
+ *                  [-pi, pi] (the domain of Sec. 2.2.1); the one-orbit-per-
+ *                  lane kernel reduces its state after every step as the
+ *                  16-lane kernels do, so a saved state resumes exactly;
+ *                  0 = continuous phases, never reduced: only the
+ *                  one-orbit-per-lane kernel provides them, so "kernel" auto
+ *                  selects it, "kernel" 2 and sode_forward_ckpt /
+ *                  sode_adjoint give SODE_EUNSUPPORTED.  Other models
+ *                  ignore the option.
  *   "observable"   0 = state (q = n values per save);
  *                  1 = Kuramoto order parameter r of Eq. (7), Sec. 2.3.1
  *                      (q = 1; Kuramoto only).
@@ -203,11 +219,9 @@ int sode_get_option(sode_t h, const char* key, int64_t* value);
  *   p    [orbits][d] or [d]     parameters (see "shared_params").
  *   out  [orbits][nsave][q]     nsave = nsteps/stride + 1; out[o][s] is the
  *                               observable of X^{s*stride}, so out[o][0] is
- *                               the observable of X0.  Kuramoto phases are
- *                               returned wrapped to [-pi, pi] by the
- *                               coupled kernels (both precisions; the
- *                               checkpoints of sode_forward_ckpt too) and
- *                               unwrapped by the plain kernel.
+ *                               the observable of X0.  Kuramoto phases
+ *                               follow the "wrap" option whichever kernel
+ *                               runs the call.
  *   nsteps >= 0, stride >= 1, nsteps % stride == 0, else SODE_EINVAL.
  *   seed  key of the Philox-4x32-10 noise stream (Sec. 2.1.2 names the
  *         Random123 family).  Normal j of orbit o at step k comes from the
@@ -226,6 +240,10 @@ int sode_integrate(sode_t h, const void* X0, const void* p, int64_t orbits, doub
  * sode_integrate_ex - sode_integrate with explicit noise addressing, so that
  * any orbit can be replayed bit-exactly, shards of one ensemble can run in
  * separate calls, and an integration can resume where an earlier one ended.
+ * The kernel of Sec. 2.1.3 (Fig. 1) takes an array of counters for the
+ * counter-based generator of Sec. 2.1.2; here the counter of every normal
+ * is a function of (step, orbit id, block), and these arguments choose the
+ * step and orbit ids a call uses.
  *
  *   orbit_offset  orbit o uses orbit id orbit_offset + o (mod 2^32) ...
  *   orbit_ids     ... unless this device array [orbits] (uint32) is given.
@@ -235,7 +253,8 @@ int sode_integrate(sode_t h, const void* X0, const void* p, int64_t orbits, doub
  *                 time is still t_k = t0 + k dt.  step_offset + nsteps must
  *                 not exceed 2^32, else SODE_EINVAL.
  * Resuming: calling again with X0 = last saved state, t0 = end time and
- * step_offset = steps already done continues the same noise path.
+ * step_offset = steps already done continues the same noise path; with
+ * "compensated" 0 (or a binary64 handle) the continuation is bit-exact.
  */
 int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, double t0,
                       double dt, int64_t nsteps, int64_t stride, uint64_t seed,
@@ -250,9 +269,13 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
  * with r of Eq. (7) (Sec. 2.3.1), accumulated in binary64.  Parameter
  * fitting over many orbits is the use the paper builds toward (Sec. 1.2).
  *
- * Handle: model "kuramoto", precision 32, method EM, n in {16, 32, 64, 128}
- * (else SODE_EUNSUPPORTED).  Noise addressing as sode_integrate_ex with
- * orbit ids orbit_offset + o and the single `seed`.  Step indices k are
+ * Handle: model "kuramoto", precision 32, method EM, wrap 1, n in
+ * {16, 32, 64, 128} (else SODE_EUNSUPPORTED).  Noise addressing as
+ * sode_integrate_ex with orbit ids orbit_offset + o and the single `seed`.
+ * With "compensated" 1 each phase is carried as hi + lo between
+ * checkpoints and lo restarts at 0 after every checkpoint, so that stepping
+ * `ckpt_every` steps from ckpt[o][c] (sode_integrate_ex with step_offset
+ * c * ckpt_every) gives ckpt[o][c+1] bit for bit.  Step indices k are
  * local to the call (k = 0 is X0); 0 <= win_lo <= win_hi <= nsteps,
  * nsteps % ckpt_every == 0, else SODE_EINVAL.
  *   ckpt  [orbits][nsteps/ckpt_every + 1][n] float, ckpt[o][c] = X^{c*ckpt_every}
@@ -266,9 +289,14 @@ int sode_forward_ckpt(sode_t h, const void* X0, const void* p, int64_t orbits, d
 /*
  * sode_adjoint - gradient of sum_o dL_dR[o] R_o with respect to p by the
  * discrete adjoint of the Euler-Maruyama map, for checkpoints written by
- * sode_forward_ckpt with the same arguments.  The noise is regenerated from
- * the Philox counter (common random numbers), segments between checkpoints
- * are recomputed bit-identically, and gradients are accumulated in binary64.
+ * sode_forward_ckpt with the same arguments: the parameter gradients that
+ * fitting a model to data over many orbits needs (the parameter-estimation
+ * use of Sec. 1.2).  The noise is regenerated from the Philox counter
+ * (common random numbers), segments between checkpoints are recomputed bit
+ * for bit as sode_forward_ckpt stepped them (with "compensated" 1 the
+ * forward pass restarts the trailing parts at 0 at every checkpoint, so a
+ * checkpoint is an exact restart point), and gradients are accumulated in
+ * binary64.
  *
  *   dL_dR            [orbits] double, or NULL for all ones.
  *   grad_p           [d] double, sum over orbits in a fixed order (may be

@@ -36,7 +36,8 @@ class Integrator:
         self.model, self.n, self.m, self.d = model, n, m, d
         self.options = {"precision": 32, "method": 0, "observable": 0, "kernel": 0,
                         "shared_params": 0, "compensated": 1, "waves_per_cu": 0,
-                        "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1, "drift": 0}
+                        "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1, "drift": 0,
+                        "ode_limit": 0, "wrap": 1}
         for k, v in options.items():
             self.set_option(k, v)
 
@@ -52,7 +53,8 @@ class Integrator:
         self.model, self.n, self.m, self.d = "custom", n, m, d
         self.options = {"precision": 32, "method": 0, "observable": 0, "kernel": 0,
                         "shared_params": 0, "compensated": 1, "waves_per_cu": 0,
-                        "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1, "drift": 0}
+                        "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1, "drift": 0,
+                        "ode_limit": 0, "wrap": 1}
         for k, v in options.items():
             self.set_option(k, v)
         return self

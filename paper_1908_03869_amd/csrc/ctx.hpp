@@ -25,6 +25,12 @@ struct sode_ctx {
     int compensated = 1;
     int drift = 0;  // Kuramoto coupling: 0 pairwise sines, 1 mean-field identity
     int gemm = sode::kRnnBf16x3;  // dense-network matrix product variant
+    // ODE methods (RK4, implicit) on a model with a diffusion: 0 = refused,
+    // 1 = integrate the ODE limit g = 0.
+    int ode_limit = 0;
+    // Kuramoto phases: 1 = every kernel returns them reduced to [-pi, pi];
+    // 0 = continuous phases (one-orbit-per-lane kernel only).
+    int wrap = 1;
     // Ragged batches: 0 = autotuned.
     int waves_per_cu = 0;
     int units_per_lane = 0;

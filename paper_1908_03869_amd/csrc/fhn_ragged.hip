@@ -25,8 +25,9 @@
 // Precision.  Near rest the recovery variable moves by ~1e-7 per step,
 // below half a binary32 ulp of w ~ 0.6, so plain binary32 updates stall and
 // drift over 10^5 steps.  With compensation (the handle's default) v and w
-// are carried as hi + lo and every increment is added with an error-free
-// two-sum.
+// are carried as hi + lo and every increment is added with Dekker's
+// Fast2Sum (exact while the state is at least the increment in magnitude,
+// see compensated_add).
 //
 // Scheduling.  The host groups instances of one shape into groups of 64/L
 // (sorted by step count inside a shape) and orders groups by decreasing
@@ -69,7 +70,7 @@ __device__ __forceinline__ float from_upper_lane_wave(float v) { return dpp_read
 // a few increments of zero, where the error it may leave is below an ulp of
 // a sum that small (~1e-9 of the state's scale).  Four operations instead of
 // the seven of the branch-free two-sum.
-__device__ __forceinline__ void two_sum_add(float& hi, float& lo, float inc)
+__device__ __forceinline__ void compensated_add(float& hi, float& lo, float inc)
 {
     const float y = inc + lo;
     const float s = hi + y;
@@ -154,8 +155,8 @@ __device__ __forceinline__ void run_group(const RaggedKernelArgs& a, int32_t g, 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if constexpr (COMP) {
-                two_sum_add(v[u], vlo[u], dv[u]);
-                two_sum_add(w[u], wlo[u], dw[u]);
+                compensated_add(v[u], vlo[u], dv[u]);
+                compensated_add(w[u], wlo[u], dw[u]);
             } else {
                 v[u] = v[u] + dv[u];
                 w[u] = w[u] + dw[u];

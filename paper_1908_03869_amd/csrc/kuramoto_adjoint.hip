@@ -25,10 +25,10 @@
 // states from its checkpoint with the same em_step() as the forward pass,
 // parks them with the normals of each step in a per-lane scratch area in
 // HBM, and sweeps them backwards.
-// Without compensation the recomputed states are bitwise those of the
-// forward pass; with it, a segment restarts from the checkpoint's leading
-// part (the trailing part, below 1e-7 rad, is dropped), which moves the
-// recomputed states by less than the binary32 trajectory error itself.
+// The recomputed states are bitwise those of the forward pass: with
+// compensation the forward pass carries each phase as hi + lo between
+// checkpoints and restarts lo at 0 after writing one, exactly as a segment
+// of the reverse pass starts from the stored hi.
 // Parameter gradients are accumulated per lane in binary64; per-orbit rows
 // are summed over orbits in binary64 in a fixed order, so the result does
 // not depend on scheduling.
@@ -108,8 +108,10 @@ __global__ __launch_bounds__(256) void forward_ckpt_kernel(const CkptArgs a)
                         racc += (double)order_parameter<P>(th);
                     if (--to_ckpt == 0) {
 #pragma unroll
-                        for (int i = 0; i < P; ++i)
+                        for (int i = 0; i < P; ++i) {
                             ck[cidx * N + i] = th[i];
+                            tl[i] = 0.0f;  // a checkpoint is an exact restart point
+                        }
                         ++cidx;
                         to_ckpt = a.every;
                     }
@@ -125,8 +127,10 @@ __global__ __launch_bounds__(256) void forward_ckpt_kernel(const CkptArgs a)
                     racc += (double)order_parameter<P>(th);
             }
 #pragma unroll
-            for (int i = 0; i < P; ++i)
+            for (int i = 0; i < P; ++i) {
                 ck[cidx * N + i] = th[i];
+                tl[i] = 0.0f;  // a checkpoint is an exact restart point
+            }
         }
     }
     if (l == 0)

@@ -9,11 +9,13 @@
 // compensation off the saved phases are the state itself, so a saved state
 // fed back in resumes bit-exactly.  With compensation on each phase is an
 // unevaluated sum hi + lo: the rounding error of every update is carried in
-// lo (two-sum), which keeps the binary32 trajectory within ~1e-9 rad of the
-// exact-arithmetic one instead of random-walking by ~1e-7 rad per step;
-// saves and checkpoints hold hi.  Once per step each phase is scaled to revolutions, the
-// argument unit of the hardware v_sin_f32, which then evaluates
-// sin(theta_j - theta_i) straight from the difference of two scaled phases.
+// lo (Fast2Sum, exact away from zero), so rounding no longer random-walks
+// the binary32 trajectory by ~1e-7 rad per step; saves and checkpoints hold
+// hi, and the checkpointed forward pass restarts lo at 0 after each
+// checkpoint, so the adjoint's recomputation from a checkpoint matches it.
+// Once per step each phase is scaled to revolutions, the argument unit of
+// the hardware v_sin_f32, which then evaluates sin(theta_j - theta_i)
+// straight from the difference of two scaled phases.
 //
 // Coupling sum S_i = sum_j sin(theta_j - theta_i).  The paper's loop (Fig. 5)
 // evaluates all N^2 sines; here every unordered pair {i, j} is evaluated

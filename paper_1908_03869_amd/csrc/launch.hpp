@@ -26,8 +26,9 @@ struct Request {
     const uint64_t* orbit_seeds;  // device, may be null
     int method;
     int observable;
-    int compensated;  // binary32 coupled kernels: two-sum compensated state
+    int compensated;  // binary32 coupled kernels: state carried as hi + lo (Fast2Sum)
     int drift;        // Kuramoto coupling sum: 0 pairwise, 1 mean-field identity
+    int wrap;         // Kuramoto: phases reduced to [-pi, pi] (the coupled kernels always do)
     void* out;  // [orbits][nsave][q]
     int* nonfinite;  // device flag raised by a NaN or infinite save (may be null)
     hipStream_t stream;
@@ -130,7 +131,7 @@ struct RaggedKernelArgs {
     const float* p;
     float* out;
     float dt, sqdt;
-    int compensated;  // two-sum state (v and w carried as hi + lo)
+    int compensated;  // v and w carried as hi + lo (Fast2Sum)
     int* nonfinite;   // device flag raised by a NaN or infinite save (may be null)
 };
 int ragged_shape_code(int lanes, int units);

@@ -33,6 +33,7 @@ PlainArgs<R> plain_args(const Request& r)
     a.d = r.d;
     a.p_per_orbit = r.p_per_orbit;
     a.observable = r.observable;
+    a.wrap = r.model == kKuramoto && r.wrap ? 1 : 0;
     a.orbits = r.orbits;
     a.stride = r.stride;
     a.nsave = r.nsave;

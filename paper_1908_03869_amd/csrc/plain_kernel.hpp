@@ -22,6 +22,7 @@ struct PlainArgs {
     const uint32_t* __restrict__ ids;
     const uint64_t* __restrict__ seeds;
     int n, m, d, p_per_orbit, observable;
+    int wrap;  // Kuramoto phases: reduced to [-pi, pi] at the start and after every step
     int64_t orbits, stride, nsave;
     R t0, dt, sqdt;
     uint64_t seed, orbit_offset, step_offset;
@@ -191,7 +192,7 @@ __device__ __forceinline__ void plain_body(const PlainArgs<R>& a)
 
     R y[CAP];
     for (int i = 0; i < n; ++i)
-        y[i] = a.X0[o * n + i];
+        y[i] = a.wrap ? dev_wrap_phase(a.X0[o * n + i]) : a.X0[o * n + i];
     plain_save(a, n, y, out);
 
     const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
@@ -250,6 +251,10 @@ __device__ __forceinline__ void plain_body(const PlainArgs<R>& a)
                 static_assert(METH == kImplicitEuler || METH == kImplicitMidpoint, "method");
                 const R c = METH == kImplicitEuler ? (R)1 : (R)0.5;
                 implicit_step<Model, R, ICAP>(n, t, a.dt, c, p, y);
+            }
+            if (a.wrap) {  // the drift is 2 pi periodic in every phase
+                for (int i = 0; i < n; ++i)
+                    y[i] = dev_wrap_phase(y[i]);
             }
         }
         plain_save(a, n, y, out + s * q);

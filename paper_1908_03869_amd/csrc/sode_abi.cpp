@@ -85,7 +85,7 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
     if (step_offset > (1ull << 32) || (uint64_t)nsteps > (1ull << 32) - step_offset)
         return SODE_EINVAL;
     if (h->model != sode::kKuramoto || h->precision != 32 || h->method != sode::kEM ||
-        !sode::adjoint_supports(h->n))
+        !h->wrap || !sode::adjoint_supports(h->n))
         return SODE_EUNSUPPORTED;
     // Checkpoints [orbits][nsteps/every + 1][n] must fit 64-bit byte offsets.
     if (orbits > 0 && nsteps / every + 1 > (INT64_MAX / 16) / orbits / h->n)
@@ -106,6 +106,14 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
 // and 81,920 at n = 5); otherwise one orbit per lane.
 int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 {
+    // RK4 and the implicit steppers integrate the ODE limit g = 0.  A model
+    // with a diffusion (every built-in model; a source-text model with
+    // m > 0) is refused unless the caller asks for that limit explicitly.
+    const bool ode_method = h->method == sode::kRK4 || h->method == sode::kImplicitEuler ||
+                            h->method == sode::kImplicitMidpoint;
+    const bool has_diffusion = h->model != sode::kCustom || h->m > 0;
+    if (ode_method && has_diffusion && !h->ode_limit)
+        return SODE_EUNSUPPORTED;
     if (h->model == sode::kCustom) {
         // Source-text models run on the run-time compiled plain stepper.
         const bool implicit = h->method == sode::kImplicitEuler || h->method == sode::kImplicitMidpoint;
@@ -115,7 +123,9 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
         *kernel = 4;
         return SODE_OK;
     }
-    const bool coupled_ok = h->model == sode::kKuramoto && h->method == sode::kEM &&
+    // The 16-lane kernels wrap the phases every step: with continuous
+    // phases requested (wrap = 0) only one orbit per lane applies.
+    const bool coupled_ok = h->model == sode::kKuramoto && h->method == sode::kEM && h->wrap &&
                             (h->precision == 32 ? sode::coupled_supports(h->n)
                                                 : sode::coupled64_supports(h->n));
     const bool matrix_ok = h->model == sode::kRNN && h->precision == 32 && h->method == sode::kEM &&
@@ -312,6 +322,14 @@ int sode_set_option(sode_t h, const char* key, int64_t value)
         if (value != 0 && value != 1)
             return SODE_EINVAL;
         h->persistent = (int)value;
+    } else if (std::strcmp(key, "ode_limit") == 0) {
+        if (value != 0 && value != 1)
+            return SODE_EINVAL;
+        h->ode_limit = (int)value;
+    } else if (std::strcmp(key, "wrap") == 0) {
+        if (value != 0 && value != 1)
+            return SODE_EINVAL;
+        h->wrap = (int)value;
     } else {
         return SODE_EINVAL;
     }
@@ -346,6 +364,10 @@ int sode_get_option(sode_t h, const char* key, int64_t* value)
         *value = h->graph;
     else if (std::strcmp(key, "persistent") == 0)
         *value = h->persistent;
+    else if (std::strcmp(key, "ode_limit") == 0)
+        *value = h->ode_limit;
+    else if (std::strcmp(key, "wrap") == 0)
+        *value = h->wrap;
     else if (std::strcmp(key, "ragged_waves_per_cu") == 0)
         *value = h->rg_last_waves;
     else if (std::strcmp(key, "ragged_units_per_lane") == 0)
@@ -407,6 +429,7 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
     r.observable = h->observable;
     r.compensated = h->compensated;
     r.drift = h->drift;
+    r.wrap = h->model == sode::kKuramoto && h->wrap ? 1 : 0;
     r.out = out;
     r.stream = static_cast<hipStream_t>(stream);
     r.nonfinite = sode::nonfinite_flag(h);

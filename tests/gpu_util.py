@@ -28,7 +28,8 @@ def run_library(w: dict, *, precision: int, kernel: str = "auto", method: str = 
                 observable: str | None = None, X0=None, p=None, nsteps=None, stride=None,
                 orbit_offset: int = 0, step_offset: int = 0, t0: float | None = None,
                 orbit_ids=None, orbit_seeds=None, shared: bool | None = None,
-                compensated: int = 1, drift: int = 0, device="cuda:0") -> np.ndarray:
+                compensated: int = 1, drift: int = 0, wrap: int = 1, ode_limit: int | None = None,
+                device="cuda:0") -> np.ndarray:
     import torch
 
     dtype = torch.float32 if precision == 32 else torch.float64
@@ -36,9 +37,13 @@ def run_library(w: dict, *, precision: int, kernel: str = "auto", method: str = 
     p = w["p"] if p is None else p
     shared = (np.asarray(p).ndim == 1) if shared is None else shared
     obs = observable or w.get("observable", "state")
+    # The ODE methods integrate the limit g = 0, which a call must ask for.
+    if ode_limit is None:
+        ode_limit = int(method in ("rk4", "implicit_euler", "implicit_midpoint"))
     it = sode.Integrator(w["model"], w["n"], w["m"], w["d"], precision=precision,
                          method=OPT[method], observable=OPT[obs], kernel=OPT[kernel],
-                         shared_params=int(shared), compensated=compensated, drift=drift)
+                         shared_params=int(shared), compensated=compensated, drift=drift,
+                         wrap=wrap, ode_limit=ode_limit)
     X0_t = torch.tensor(np.ascontiguousarray(X0), dtype=dtype, device=device)
     p_t = torch.tensor(np.ascontiguousarray(p), dtype=dtype, device=device)
     ids = orbit_ids if orbit_ids is not None else w.get("orbit_ids")

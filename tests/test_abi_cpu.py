@@ -210,6 +210,78 @@ def test_adjoint_entry_points_pointers_and_support():
     abi.sode_destroy(h)
 
 
+@pytest.mark.parametrize("model,n,m,d", [("kuramoto", 4, 4, 9), ("ou", 3, 3, 3), ("fhn", 6, 3, 5),
+                                         ("gbm", 2, 2, 2), ("rnn", 3, 3, 13)])
+@pytest.mark.parametrize("method", [1, 3, 4])
+def test_ode_methods_need_ode_limit_on_models_with_noise(model, n, m, d, method):
+    """RK4 and the implicit steppers integrate the ODE limit g = 0: a model
+    with a diffusion is refused unless "ode_limit" is set.  Zero orbits reach
+    the kernel choice without touching the device."""
+    st, h = abi.sode_create(model, n, m, d)
+    try:
+        assert abi.sode_get_option(h, "ode_limit") == (0, 0)
+        abi.sode_set_option(h, "method", method)
+        assert _call(h, orbits=0) == abi.SODE_EUNSUPPORTED
+        assert _call(h) == abi.SODE_EUNSUPPORTED
+        assert abi.sode_set_option(h, "ode_limit", 1) == 0
+        assert abi.sode_get_option(h, "ode_limit") == (0, 1)
+        assert _call(h, orbits=0) == abi.SODE_OK
+        abi.sode_set_option(h, "method", 0)  # Euler-Maruyama never needs it
+        abi.sode_set_option(h, "ode_limit", 0)
+        assert _call(h, orbits=0) == abi.SODE_OK
+        assert abi.sode_set_option(h, "ode_limit", 2) == abi.SODE_EINVAL
+    finally:
+        abi.sode_destroy(h)
+
+
+def test_ode_methods_on_source_text_models():
+    """A source-text ODE (m = 0) takes RK4 and the implicit steppers as is;
+    with Wiener processes it needs "ode_limit" like the built-in models."""
+    for m, diffusion in ((0, None), (1, "gx[0] = p[0] * xi[0];")):
+        st, h = abi.sode_create_custom("f[0] = -y[0];", diffusion, 1, m, 1)
+        assert st == 0
+        try:
+            for method in (1, 3, 4):
+                abi.sode_set_option(h, "method", method)
+                assert _call(h, orbits=0) == (abi.SODE_OK if m == 0 else abi.SODE_EUNSUPPORTED)
+                abi.sode_set_option(h, "ode_limit", 1)
+                assert _call(h, orbits=0) == abi.SODE_OK
+                abi.sode_set_option(h, "ode_limit", 0)
+        finally:
+            abi.sode_destroy(h)
+
+
+def test_wrap_option_fixes_the_phase_convention():
+    """"wrap" 1 (default): every kernel returns reduced phases.  "wrap" 0
+    (continuous phases) is served by the one-orbit-per-lane kernel only:
+    auto selection takes it, an explicit 16-lane request and the
+    checkpointed forward pass / adjoint (whose checkpoints are reduced) are
+    refused."""
+    st, h = abi.sode_create("kuramoto", 64, 64, 129)
+    try:
+        assert abi.sode_get_option(h, "wrap") == (0, 1)
+        abi.sode_set_option(h, "kernel", 2)
+        assert _call(h, orbits=0) == abi.SODE_OK
+        assert abi.sode_set_option(h, "wrap", 0) == 0
+        assert abi.sode_get_option(h, "wrap") == (0, 0)
+        assert _call(h, orbits=0) == abi.SODE_EUNSUPPORTED
+        abi.sode_set_option(h, "kernel", 0)
+        assert _call(h, orbits=0) == abi.SODE_OK
+        abi.sode_set_option(h, "precision", 64)
+        assert _call(h, orbits=0) == abi.SODE_OK
+        assert abi.sode_set_option(h, "wrap", 3) == abi.SODE_EINVAL
+    finally:
+        abi.sode_destroy(h)
+    st, h = abi.sode_create("kuramoto", 32, 32, 65)
+    try:
+        assert _ckpt(h, orbits=0, X0=None, p=None, ckpt=None, R=None) == abi.SODE_OK
+        abi.sode_set_option(h, "wrap", 0)
+        assert _ckpt(h) == abi.SODE_EUNSUPPORTED
+        assert _adj(h) == abi.SODE_EUNSUPPORTED
+    finally:
+        abi.sode_destroy(h)
+
+
 def _ragged(h, descs, x0_len=1000, p_len=1000, out_len=10**7, dt=1e-3):
     arr = (abi.SodeInstance * len(descs))(*descs) if descs else None
     return abi.sode_integrate_ragged(h, arr, len(descs), FAKE, x0_len, FAKE, p_len, FAKE, out_len,

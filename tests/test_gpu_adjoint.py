@@ -15,6 +15,11 @@ from gpu_util import as_received, log, run_library, threads
 pytestmark = pytest.mark.gpu
 
 
+def gradient_blocks(n):
+    """Index ranges of K, the frequencies and the noise strengths in p."""
+    return {"K": slice(0, 1), "omega": slice(1, n + 1), "sigma": slice(n + 1, 2 * n + 1)}
+
+
 def _tensors(w, rows=None):
     import torch
     X0 = w["X0"] if rows is None else w["X0"][rows]
@@ -23,27 +28,59 @@ def _tensors(w, rows=None):
             torch.tensor(p, dtype=torch.float32, device="cuda"))
 
 
-def _integrator(n):
+def _integrator(n, **opts):
     import paper_1908_03869_amd as sode
-    return sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, shared_params=1)
+    return sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, shared_params=1, **opts)
 
 
 def test_checkpoints_equal_integrated_states(gpu):
-    """The checkpointed forward pass steps exactly like sode_integrate, and
-    its binary64 window average matches the oracle's."""
+    """Without compensation the checkpointed forward pass steps exactly like
+    one sode_integrate call, and its binary64 window average matches the
+    oracle's."""
     import oracle
     w = workloads.kuramoto_adjoint(orbits=40)
     X0, p = _tensors(w)
-    it = _integrator(32)
+    it = _integrator(32, compensated=0)
     log("forward_ckpt vs integrate, 40 orbits x 600 steps")
     ckpt, R = it.forward_ckpt(X0, p, 0.0, w["dt"], 600, 100, 300, 600, w["seed"])
     it.sync()
     states = run_library(dict(w, observable="state"), precision=32, kernel="coupled",
-                         nsteps=600, stride=100, shared=True)
+                         nsteps=600, stride=100, shared=True, compensated=0)
     np.testing.assert_array_equal(ckpt.double().cpu().numpy(), states)
     Rref, _, _ = oracle.kuramoto_adjoint(32, as_received(w["X0"], 32), as_received(w["p"], 32),
                                          0.0, w["dt"], 600, 300, 600, w["seed"], per_orbit=False)
     assert np.max(np.abs(R.cpu().numpy() - Rref)) <= 1e-5
+
+
+def test_compensated_checkpoints_are_exact_restart_points(gpu):
+    """The full workload (4096 orbits, 10^4 steps, compensated): stepping
+    ckpt_every steps from checkpoint c with sode_integrate_ex (compensated,
+    step_offset c * ckpt_every) reproduces checkpoint c + 1 bit for bit, for
+    every c -- so the adjoint, which restarts every segment from its
+    checkpoint, recomputes exactly the states the forward pass integrated."""
+    import torch
+    w = workloads.kuramoto_adjoint()
+    X0, p = _tensors(w)
+    it = _integrator(32)
+    assert it.get_option("compensated") == 1
+    every = w["ckpt_every"]
+    log("forward_ckpt compensated, 4096 orbits x 1e4 steps, segment restarts")
+    ckpt, _ = it.forward_ckpt(X0, p, 0.0, w["dt"], w["nsteps"], every, w["win_lo"], w["win_hi"],
+                              w["seed"])
+    seg = _integrator(32, observable="state", kernel="coupled")
+    nck = ckpt.shape[1]
+    got = torch.empty_like(ckpt)
+    got[:, 0] = ckpt[:, 0]
+    out = torch.empty((ckpt.shape[0], 2, 32), dtype=torch.float32, device="cuda")
+    for c in range(nck - 1):
+        start = ckpt[:, c].contiguous()
+        seg.integrate(start, p, c * every * w["dt"], w["dt"], every, every, w["seed"],
+                      step_offset=c * every, out=out)
+        got[:, c + 1] = out[:, 1]
+    seg.sync()
+    it.sync()
+    bad = (got != ckpt).any(dim=2).any(dim=0).nonzero().flatten().tolist()
+    assert not bad, f"checkpoints not reproduced: {bad[:10]}"
 
 
 def test_adjoint_matches_fp64_oracle_adjoint(gpu):
@@ -125,6 +162,13 @@ def test_adjoint_full_workload_vs_stored_oracle_gradient(gpu):
     print(f"loss {loss:.8f} (oracle {ref['loss']:.8f}); gradient rel L2 error {rel:.3e}")
     assert abs(loss - ref["loss"]) <= 1e-4 * ref["loss"]
     assert rel <= 1e-3, rel
+    # Each block of p = (K, omega_1..32, p_1..32) on its own: the K entry
+    # dominates the whole vector, so the frequency and noise blocks are held
+    # to the bound separately.
+    for name, blk in gradient_blocks(32).items():
+        e = np.linalg.norm(g[blk] - gref[blk]) / np.linalg.norm(gref[blk])
+        print(f"block {name}: rel L2 error {e:.3e} (|g_ref| = {np.linalg.norm(gref[blk]):.3e})")
+        assert e <= 1e-3, (name, e)
 
 
 def test_adjoint_full_workload_vs_central_differences(gpu):

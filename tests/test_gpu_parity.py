@@ -55,8 +55,11 @@ def test_plain_models_fp64(gpu, model, n, m, d, p, x0):
     log(f"plain fp64 {model} n={n}")
     got = run_library(w, precision=64, kernel="plain")
     want = run_oracle(w)
-    scale = np.maximum(1.0, np.abs(want))
-    assert np.max(np.abs(got - want) / scale) <= 1e-10
+    if model == "kuramoto":  # returned reduced to [-pi, pi]; the oracle never wraps
+        assert circular_diff(got, want).max() <= 1e-10
+    else:
+        scale = np.maximum(1.0, np.abs(want))
+        assert np.max(np.abs(got - want) / scale) <= 1e-10
 
 
 FHN_P = [0.7, 0.8, 0.08, 0.1, 0.05]
@@ -326,6 +329,28 @@ def test_edge_sizes(gpu, precision, kernel):
     ref = run_oracle(w, nsteps=300, stride=300, precision=precision)
     tol = 1e-10 if precision == 64 else 1e-4
     assert circular_diff(one, ref).max() <= tol
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_phase_convention_does_not_depend_on_the_kernel(gpu, precision):
+    """With "wrap" 1 every kernel returns Kuramoto phases in [-pi, pi] (plain
+    and 16-lane alike, whatever auto selection picks); with "wrap" 0 the
+    one-orbit-per-lane kernel returns continuous phases, equal to the
+    oracle's (which never wraps) without reduction."""
+    w = dict(_grid(3, 5, 16, 2000), observable="state")
+    w["X0"] = w["X0"] + 4 * math.pi  # initial phases outside [-pi, pi]
+    tol = 1e-10 if precision == 64 else 1e-3
+    want = run_oracle(w, precision=precision)
+    assert np.abs(want).max() > math.pi + 1.0  # the oracle's phases leave the range
+    for kernel in ("plain", "coupled", "auto"):
+        log(f"wrap=1 {kernel} fp{precision}")
+        got = run_library(w, precision=precision, kernel=kernel)
+        lim = math.pi * (1 + 2.0 ** -20)
+        assert np.abs(got).max() <= lim, kernel
+        assert circular_diff(got, want).max() <= tol, kernel
+    log(f"wrap=0 auto fp{precision}")
+    cont = run_library(w, precision=precision, wrap=0)
+    assert np.abs(cont - want).max() <= tol
 
 
 def test_shared_params_equal_per_orbit_rows(gpu):
