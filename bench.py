@@ -479,6 +479,9 @@ def parse():
     ap.add_argument("--paper-sweep", type=int, default=0, metavar="REPS",
                     help="instead of the benchmark line, time the Sec. 2.2.1 speed protocol "
                          "(N x M x precision x drift form), REPS runs per case")
+    ap.add_argument("--op-rates", action="store_true",
+                    help="instead of the benchmark line, measure the issue cost of each "
+                         "instruction class (one JSON line per class and waves per SIMD)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB, so that "
                          "HBM byte counters can be scaled against a kernel of known traffic")
@@ -498,6 +501,9 @@ def main():
     import paper_1908_03869_amd as sode
 
     dev = torch.device("cuda:0")
+    if args.op_rates:
+        op_rates()
+        return
     if args.paper_sweep:
         paper_sweep(sode, torch, workloads, dev, args.paper_sweep)
         return
