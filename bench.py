@@ -51,6 +51,74 @@ SLOTS = {"valu": 1.0, "trans": 4.0, "imul": 2.0}
 COUPLED_N64_HBM_BYTES = 50.97e6 + 53.01e6
 
 
+# Binary64 VALU issue: a SIMD retires 16 lanes of v_fma_f64 per clock, so the
+# chip issues 256 * 4 * 16 * 2.4e9 = 3.93e13 binary64 FMA lane-slots/s, the
+# published 78.6 TFLOP/s binary64 vector peak.
+FP64_FMA_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# Issue cost in binary64 FMA slots of one call of each device-library
+# binary64 function, of a v_mad_u64_u32 and of a v_bitop3_b32: measured
+# wave64 issue cycles of each divided by those of one v_fma_f64 (the op-rate
+# microbenchmark, bench.py --op-rates, four waves per SIMD: sin/cos 258.7,
+# log 360.8, sqrt 88.6, v_mad_u64_u32 4.66, v_bitop3_b32 3.04 cycles against
+# 4.30 for v_fma_f64).
+FP64_SLOTS = {"sin": 60.2, "log": 83.9, "sqrt": 20.6, "fma64": 1.0, "imul": 1.08, "valu32": 0.71}
+
+
+def fp64_slots_per_orbit_step(n: int) -> dict:
+    """Minimal work of one binary64 Euler-Maruyama step of one n-oscillator
+    Kuramoto orbit, each unordered pair's sine once, in binary64 FMA slots."""
+    pairs = n * (n - 1) // 2
+    blocks = (n + 3) // 4
+    bm = (n + 1) // 2
+    counts = {
+        # per pair: the sine, one difference and two accumulations
+        "sin": pairs + 2 * bm,            # plus cos and sin of each Box-Muller pair
+        "log": bm, "sqrt": bm,
+        # per pair 3 ops; per oscillator: two FMAs for the increment, the
+        # state add and the 2 pi wrap (scale, round, two FMAs); per
+        # Box-Muller pair: two conversions, two scalings, radius, two products
+        "fma64": pairs * 3 + n * 7 + bm * 7,
+        # per Philox block: ten rounds of two 32 x 32 -> 64 products
+        # (v_mad_u64_u32) and two three-way XORs
+        "imul": blocks * 20,
+        "valu32": blocks * 20,
+    }
+    counts["slots"] = sum(counts[k] * FP64_SLOTS[k] for k in FP64_SLOTS)
+    return counts
+
+
+def host_threads() -> tuple[int, int]:
+    """(CPUs in this process's affinity mask, threads the multi-threaded
+    oracle runs use).  The oracle legs run one thread per CPU of the mask,
+    at most 16 (one GPU's share of the shared hosts this is measured on)."""
+    visible = len(os.sched_getaffinity(0))
+    return visible, max(1, min(16, visible))
+
+
+def stratified_instances(units, nsteps, bins: int = 8) -> np.ndarray:
+    """One instance per cell of a bins x bins grid of (unit count, step
+    count) quantile bins, the first in index order; cells with no instance
+    are filled with the first instances not yet taken, so the sample always
+    has bins^2 instances (if the batch has that many)."""
+    units, nsteps = np.asarray(units), np.asarray(nsteps)
+    qu = np.quantile(units, np.linspace(0, 1, bins + 1)[1:-1])
+    qs = np.quantile(nsteps, np.linspace(0, 1, bins + 1)[1:-1])
+    cu = np.searchsorted(qu, units, side="right")
+    cs = np.searchsorted(qs, nsteps, side="right")
+    taken, seen = [], set()
+    for i in range(len(units)):
+        cell = (int(cu[i]), int(cs[i]))
+        if cell not in seen:
+            seen.add(cell)
+            taken.append(i)
+    for i in range(len(units)):
+        if len(taken) >= bins * bins:
+            break
+        if i not in taken:
+            taken.append(i)
+    return np.sort(np.asarray(taken[:bins * bins], dtype=np.int64))
+
+
 def algorithmic_slots_per_orbit_step(n: int, compensated: bool = True) -> dict:
     """Minimal work of one Euler-Maruyama step of one n-oscillator orbit with
     pairwise sine coupling (each unordered pair once), Philox-4x32-10 noise
@@ -77,10 +145,14 @@ def algorithmic_slots_per_orbit_step(n: int, compensated: bool = True) -> dict:
     return counts
 
 
-def adjoint_leg(sode, torch, workloads, dev, reps: int = 3) -> dict:
+def adjoint_leg(sode, torch, workloads, dev, reps: int = 3, cpu: bool = True) -> dict:
     """Forward (with checkpoints) and backward (adjoint) times of the n = 32
     gradient workload: 4096 orbits sharing (omega, K, sigma), 10^4 steps,
-    checkpoints every 100, R = mean r over steps 5000..10000."""
+    checkpoints every 100, R = mean r over steps 5000..10000, loss = mean
+    (R - 0.6)^2.  Error: relative L2 error of the loss gradient against the
+    FP64 oracle adjoint of the same orbits (stored with the tests), over the
+    whole vector and per block (K, frequencies, noise strengths).  CPU
+    baseline: the FP64 oracle adjoint (forward and reverse) on 8 orbits."""
     w = workloads.kuramoto_adjoint()
     n = w["n"]
     X0 = torch.tensor(w["X0"], dtype=torch.float32, device=dev)
@@ -105,12 +177,37 @@ def adjoint_leg(sode, torch, workloads, dev, reps: int = 3) -> dict:
             bwd.append(e1b.elapsed_time(e2))
     f, b = float(np.median(fwd)), float(np.median(bwd))
     orbits = X0.shape[0]
-    return {"workload": "kuramoto_adjoint_n32", "orbits": orbits, "nsteps": w["nsteps"],
-            "forward_ms": f, "backward_ms": b, "ratio_backward_over_forward": b / f,
-            "ratio_total_over_forward": (f + b) / f,
-            "forward_orbit_steps_per_s": orbits * w["nsteps"] / (f * 1e-3),
-            "loss": float(((R - w["target"]) ** 2).mean()),
-            "grad_norm": float(grad.norm())}
+    g = grad.double().cpu().numpy()
+    res = {"workload": "kuramoto_adjoint_n32", "orbits": orbits, "nsteps": w["nsteps"],
+           "forward_ms": f, "backward_ms": b, "ratio_backward_over_forward": b / f,
+           "ratio_total_over_forward": (f + b) / f,
+           "forward_orbit_steps_per_s": orbits * w["nsteps"] / (f * 1e-3),
+           "loss": float(((R - w["target"]) ** 2).mean()),
+           "grad_norm": float(np.linalg.norm(g))}
+    golden = os.path.join(ROOT, "tests", "golden", "kuramoto_adjoint_n32.json")
+    with open(golden) as fh:
+        gref = np.array(json.load(fh)["grad"])
+    blocks = {"K": slice(0, 1), "omega": slice(1, n + 1), "sigma": slice(n + 1, 2 * n + 1)}
+    res["error"] = {
+        "grad_rel_l2": float(np.linalg.norm(g - gref) / np.linalg.norm(gref)),
+        "per_block_rel_l2": {k: float(np.linalg.norm(g[s] - gref[s]) / np.linalg.norm(gref[s]))
+                             for k, s in blocks.items()},
+        "tolerance": 1e-3, "reference": "FP64 oracle adjoint, all 4096 orbits (stored)"}
+    if cpu:
+        import oracle
+        rows = np.arange(8)
+        c0 = time.perf_counter()
+        oracle.kuramoto_adjoint(n, w["X0"][rows].astype(np.float32).astype(np.float64),
+                                w["p"].astype(np.float32).astype(np.float64), 0.0, w["dt"],
+                                w["nsteps"], w["win_lo"], w["win_hi"], w["seed"], per_orbit=False)
+        cs = time.perf_counter() - c0
+        res["cpu_baseline"] = {
+            "value": len(rows) * w["nsteps"] / cs, "unit": "orbit*steps/s (forward + adjoint)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{len(rows)} orbits x {w['nsteps']} steps, FP64 forward and reverse "
+                      f"pass, single-threaded, {cs:.1f} s"}
+        res["gpu_orbit_steps_per_s_forward_plus_adjoint"] = orbits * w["nsteps"] / ((f + b) * 1e-3)
+    return res
 
 
 def ragged_alone_ms(sode, torch, w, j: int, cfg, dev) -> float:
@@ -135,7 +232,7 @@ def ragged_alone_ms(sode, torch, w, j: int, cfg, dev) -> float:
     return t
 
 
-def ragged_leg(sode, torch, workloads, dev, reps: int = 5) -> dict:
+def ragged_leg(sode, torch, workloads, dev, reps: int = 5, cpu: bool = True) -> dict:
     """Makespan of the 4096-instance FitzHugh-Nagumo batch in one persistent,
     graph-captured launch (autotuned on the first, untimed call), and the
     slowest instance run alone: the batch cannot finish before it."""
@@ -172,17 +269,56 @@ def ragged_leg(sode, torch, workloads, dev, reps: int = 5) -> dict:
         t = ragged_alone_ms(sode, torch, w, j, cfg, dev)
         if t > alone:
             alone, jc = t, j
-    return {"workload": "fhn_ragged_4096", "instances": b.count, "unit_steps": unit_steps,
-            "makespan_ms": ms, "unit_steps_per_s": unit_steps / (ms * 1e-3),
-            "waves_per_cu": cfg[0], "units_per_lane": cfg[1],
-            "critical_instance_alone_ms": alone,
-            "critical_instance": {"units": int(w["units"][jc]), "nsteps": int(w["nsteps"][jc])},
-            "makespan_over_critical": ms / alone}
+    res = {"workload": "fhn_ragged_4096", "instances": b.count, "unit_steps": unit_steps,
+           "makespan_ms": ms, "unit_steps_per_s": unit_steps / (ms * 1e-3),
+           "waves_per_cu": cfg[0], "units_per_lane": cfg[1],
+           "critical_instance_alone_ms": alone,
+           "critical_instance": {"units": int(w["units"][jc]), "nsteps": int(w["nsteps"][jc])},
+           "makespan_over_critical": ms / alone}
+    if cpu:
+        # Error on 64 instances stratified by unit and step count: per
+        # instance max_s |dX|_inf / max(1, max_s |X|_inf) against the FP64
+        # oracle on the float32-rounded inputs the kernel received.
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        got_all = out.double().cpu().numpy()
+        sel = stratified_instances(w["units"], w["nsteps"])
+        X0r = b.pack(w["X0"]).astype(np.float32).astype(np.float64)
+        pr = b.pack(w["params"]).astype(np.float32).astype(np.float64)
+
+        def ref_of(i):
+            a, nn = int(b.x0_offset[i]), int(b.n[i])
+            return oracle.integrate("fhn", nn, nn // 2, 5, X0r[a:a + nn][None], pr[5 * i:5 * i + 5],
+                                    0.0, w["dt"], int(b.nsteps[i]), int(b.stride[i]), w["seed"],
+                                    orbit_ids=[int(i)])[0]
+
+        _, nthreads = host_threads()
+        with ThreadPoolExecutor(max_workers=nthreads) as ex:
+            refs = list(ex.map(ref_of, sel))
+        errs = np.array([np.abs(b.unpack(got_all, int(i)) - r).max() / max(1.0, np.abs(r).max())
+                         for i, r in zip(sel, refs)])
+        res["error"] = {"max_rel": float(errs.max()), "median_rel": float(np.median(errs)),
+                        "within_tolerance": int((errs <= 1e-4).sum()), "instances": len(sel),
+                        "tolerance": 1e-4, "sample": "64 instances stratified by units x steps"}
+        # CPU baseline: the oracle single-threaded on every 4th instance of the sample.
+        sub = sel[::4]
+        c0 = time.perf_counter()
+        for i in sub:
+            ref_of(i)
+        cs = time.perf_counter() - c0
+        us = int((w["units"][sub] * w["nsteps"][sub]).sum())
+        res["cpu_baseline"] = {"value": us / cs, "unit": "unit*steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{len(sub)} of the stratified instances ({us} unit-steps), "
+                                         f"FP64, single-threaded, {cs:.1f} s"}
+    return res
 
 
-def rnn_leg(sode, torch, workloads, dev, gemms=("bf16", "bf16x3", "fp32")) -> dict:
+def rnn_leg(sode, torch, workloads, dev, gemms=("bf16", "bf16x3", "fp32"), cpu: bool = True) -> dict:
     """The n = 256 dense-network workload (8192 orbits, 5000 steps) with each
-    matrix-product variant; MFMA work = 2 n^2 flops per orbit-step."""
+    matrix-product variant; MFMA work = 2 n^2 flops per orbit-step.  Error
+    per variant: relative L2 norm of the final-state difference per orbit
+    against the FP64 oracle (float32-rounded inputs), max and median over 64
+    orbits (every 128th); bound 1e-2.  CPU baseline: the oracle on 4 orbits."""
     w = workloads.rnn_dense()
     n = w["n"]
     X0 = torch.tensor(w["X0"], dtype=torch.float32, device=dev)
@@ -190,6 +326,25 @@ def rnn_leg(sode, torch, workloads, dev, gemms=("bf16", "bf16x3", "fp32")) -> di
     orbits = X0.shape[0]
     stream = torch.cuda.current_stream()
     res = {"workload": "rnn_dense_n256", "orbits": orbits, "nsteps": w["nsteps"]}
+    rows = np.arange(0, orbits, orbits // 64)
+    ref = None
+    if cpu:
+        import oracle
+        _, nthreads = host_threads()
+        Xr = w["X0"].astype(np.float32).astype(np.float64)
+        pr = w["p"].astype(np.float32).astype(np.float64)
+        ref = oracle.integrate_parallel("rnn", n, n, w["d"], Xr[rows], pr, 0.0, w["dt"], w["nsteps"],
+                                        w["nsteps"], w["seed"], threads=nthreads,
+                                        orbit_ids=rows.astype(np.uint32))[:, -1]
+        sub = rows[:4]
+        c0 = time.perf_counter()
+        oracle.integrate("rnn", n, n, w["d"], Xr[sub], pr, 0.0, w["dt"], w["nsteps"], w["nsteps"],
+                         w["seed"], orbit_ids=sub.astype(np.uint32))
+        cs = time.perf_counter() - c0
+        res["cpu_baseline"] = {"value": len(sub) * w["nsteps"] / cs, "unit": "orbit*steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{len(sub)} orbits x {w['nsteps']} steps, FP64, "
+                                         f"single-threaded, {cs:.1f} s"}
     for gemm in gemms:
         products = 3 if gemm == "bf16x3" else 1
         it = sode.Integrator("rnn", n, n, w["d"], precision=32, shared_params=1,
@@ -205,6 +360,119 @@ def rnn_leg(sode, torch, workloads, dev, gemms=("bf16", "bf16x3", "fp32")) -> di
         flops = 2.0 * n * n * orbits * w["nsteps"] * products
         res[gemm] = {"ms": ms, "orbit_steps_per_s": orbits * w["nsteps"] / (ms * 1e-3),
                      "mfma_tflops": flops / (ms * 1e-3) / 1e12}
+        if ref is not None:
+            got = out[:, -1][torch.as_tensor(rows, device=out.device)].double().cpu().numpy()
+            rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            res[gemm]["error"] = {"max_rel_l2": float(rel.max()), "median_rel_l2": float(np.median(rel)),
+                                  "tolerance": 1e-2, "orbits": len(rows)}
+        it.close()
+    return res
+
+
+def small_fp64_leg(sode, torch, workloads, dev, reps: int = 5, cpu: bool = True) -> dict:
+    """The n = 4 binary64 ensemble: 1024 orbits (32 coupling values x 32
+    seeds, the orbits of one seed sharing its Brownian path), dt = 1e-3,
+    10^4 steps, state saved every 100 steps.  Kernel time (HIP events, median
+    of `reps` after a warm-up) on the automatically chosen kernel (16 lanes
+    per orbit) and on one orbit per lane; error = max circular |dtheta| over
+    all 1024 orbits and saves against the FP64 oracle (bound 1e-10), which
+    is also timed single-threaded on all of them.
+
+    FP64 roofline: the work of one orbit-step counted from the formulation
+    (each unordered pair's sine once, the Box-Muller functions of m/2 pairs,
+    the per-pair and per-oscillator arithmetic, one Philox block), each
+    class priced in binary64 FMA issue slots by its measured cost, against
+    the chip's 256 x 4 x 16 x 2.4e9 = 3.93e13 binary64 FMA lane-slots/s
+    (78.6 TFLOP/s).  1024 orbits are 16 waves on one lane each, or 256 on
+    16 lanes: far fewer than the chip's 1024 SIMDs, so the fraction also
+    says how much of the chip this small ensemble can occupy."""
+    w = workloads.kuramoto_small()
+    n, orbits, nsteps, stride = w["n"], w["X0"].shape[0], w["nsteps"], w["stride"]
+    X0 = torch.tensor(w["X0"], dtype=torch.float64, device=dev)
+    p = torch.tensor(w["p"], dtype=torch.float64, device=dev)
+    ids = torch.tensor(w["orbit_ids"].astype(np.int32), device=dev)
+    seeds = torch.tensor(w["orbit_seeds"].astype(np.int64), device=dev)
+    stream = torch.cuda.current_stream()
+    res = {"workload": "kuramoto_small_n4_fp64", "orbits": orbits, "n": n, "nsteps": nsteps,
+           "dt": w["dt"], "stride": stride}
+    outs = {}
+    for kernel in ("auto", "plain"):
+        it = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=64, kernel=kernel)
+        out = torch.empty((orbits, nsteps // stride + 1, n), dtype=torch.float64, device=dev)
+        call = lambda: it.integrate(X0, p, 0.0, w["dt"], nsteps, stride, w["seed"], orbit_ids=ids,
+                                    orbit_seeds=seeds, out=out)
+        call()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        name = "lanes16" if kernel == "auto" else "plain"
+        res[name] = {"kernel_ms": ms, "orbit_steps_per_s": orbits * nsteps / (ms * 1e-3),
+                     "us_per_step": ms * 1e3 / nsteps}
+        outs[name] = out.cpu().numpy()
+        it.close()
+    work = fp64_slots_per_orbit_step(n)
+    for name in ("lanes16", "plain"):
+        achieved = work["slots"] * orbits * nsteps / (res[name]["kernel_ms"] * 1e-3)
+        res[name]["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
+                                 "peak": FP64_FMA_SLOTS_PER_S / 1e12,
+                                 "unit": "T binary64 FMA lane-slots/s", "frac": achieved / FP64_FMA_SLOTS_PER_S,
+                                 "slots_per_orbit_step": work["slots"]}
+    if cpu:
+        import oracle
+        c0 = time.perf_counter()
+        ref = oracle.integrate("kuramoto", n, n, 2 * n + 1, w["X0"], w["p"], 0.0, w["dt"], nsteps,
+                               stride, w["seed"], orbit_ids=w["orbit_ids"],
+                               orbit_seeds=w["orbit_seeds"])
+        cs = time.perf_counter() - c0
+        res["cpu_baseline"] = {"value": orbits * nsteps / cs, "unit": "orbit*steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"all {orbits} orbits x {nsteps} steps, FP64, "
+                                         f"single-threaded, {cs:.1f} s"}
+        for name in ("lanes16", "plain"):
+            d = np.abs(np.remainder(outs[name] - ref + math.pi, 2 * math.pi) - math.pi)
+            res[name]["error"] = {"max_circular_dtheta": float(d.max()), "tolerance": 1e-10}
+    return res
+
+
+def grid_fp64_leg(sode, torch, w, X0, p, dev, bsteps: int, rows, ref_rows=None) -> dict:
+    """Binary64 kernels on the n = 64 grid ensemble, `bsteps` steps (their
+    per-step cost does not depend on the step count): one orbit per lane (the
+    plain FP64 per-orbit baseline) and 16 lanes per orbit.  Error: max |dr| at
+    the last step over the sampled orbits `rows` against the oracle."""
+    import oracle
+    n, orbits, stride = w["n"], X0.shape[0], w["stride"]
+    X64, p64 = X0.double(), p.double()
+    stream = torch.cuda.current_stream()
+    if ref_rows is None:
+        ref_rows = oracle.integrate_parallel(
+            "kuramoto", n, n, 2 * n + 1, w["X0"][rows].astype(np.float32).astype(np.float64),
+            w["p"][rows].astype(np.float32).astype(np.float64), 0.0, w["dt"], bsteps, bsteps,
+            w["seed"], threads=host_threads()[1], orbit_ids=rows, observable="kuramoto_r")[:, -1, 0]
+    res = {}
+    for kernel, name in (("plain", "plain_fp64"), ("coupled", "lanes16_fp64")):
+        it = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=64, observable="kuramoto_r",
+                             kernel=kernel)
+        out = torch.empty((orbits, bsteps // stride + 1, 1), dtype=torch.float64, device=dev)
+        it.integrate(X64[:256], p64[:256], 0.0, w["dt"], stride, stride, w["seed"])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        it.integrate(X64, p64, 0.0, w["dt"], bsteps, stride, w["seed"], out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        r = out[:, -1, 0].cpu().numpy()[rows]
+        res[name] = {"value": orbits * bsteps / (ms * 1e-3), "unit": "orbit*steps/s", "nsteps": bsteps,
+                     "kernel_ms": ms,
+                     "error": {"max_abs_dr": float(np.abs(r - ref_rows).max()), "orbits": len(rows),
+                               "tolerance": 1e-4}}
         it.close()
     return res
 
@@ -297,16 +565,17 @@ def next_rows(sode, torch, dev, reps: int = 3) -> None:
          over_builtin=ms / builtin)
 
 
-def op_rates(waves_per_simd=(1, 2, 4, 8)) -> None:
+def op_rates(waves_per_simd=(1, 2, 4)) -> None:
     """Issue cost of each instruction class on gfx950, measured by the
-    op-rate microbenchmark (csrc/op_rates.hip, built as libop_rates.so): for
-    every class and W waves per SIMD (blocks of 4 waves, 256 W blocks), the
-    shader-clock cycles of each wave's loop give the SIMD cycles one wave64
-    instruction (or one library call) occupies, cycles / (instructions per
-    wave x W), and 64 lanes over that cost give lanes per clock per SIMD.
-    The effective clock is the mean cycle count over the launch duration.
-    One JSON line per (class, W)."""
+    op-rate microbenchmark (csrc/op_rates.hip, built as libop_rates.so): one
+    workgroup per CU with W waves on each SIMD, all starting together; the
+    span of a workgroup's loops gives the SIMD cycles of W waves'
+    instructions, so one wave64 instruction (or one library call) occupies
+    span / (W x instructions per wave) cycles, and 64 lanes over that cost
+    give lanes per clock per SIMD.  The clock is the span over the launch
+    duration.  One JSON line per (class, W)."""
     import ctypes
+    import torch
     from paper_1908_03869_amd import build as hipbuild
 
     if not os.path.exists(hipbuild.OP_RATES_LIB):
@@ -320,20 +589,21 @@ def op_rates(waves_per_simd=(1, 2, 4, 8)) -> None:
     L.op_rates_run.restype = ctypes.c_int
     L.op_rates_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
     for op in range(L.op_rates_count()):
         name = L.op_rates_name(op).decode()
         library = "library call" in name
         iters = 100 if library else 4000
         for W in waves_per_simd:
-            cyc, ms = ctypes.c_double(), ctypes.c_double()
-            rc = L.op_rates_run(op, 256 * W, 4, iters, ctypes.byref(cyc), ctypes.byref(ms))
+            span, ms = ctypes.c_double(), ctypes.c_double()
+            rc = L.op_rates_run(op, cus, 4 * W, iters, ctypes.byref(span), ctypes.byref(ms))
             if rc != 0:
                 raise RuntimeError(f"op_rates_run({name}) failed: {rc}")
             ops = L.op_rates_ops_per_wave(op, iters)
-            cost = cyc.value / (ops * W)
+            cost = span.value / (ops * W)
             print(json.dumps({"op_rates": name, "waves_per_simd": W, "iters": iters,
                               "cycles_per_wave_op": cost, "lanes_per_clk_per_simd": 64.0 / cost,
-                              "clock_ghz": cyc.value / (ms.value * 1e6), "kernel_ms": ms.value}),
+                              "clock_ghz": span.value / (ms.value * 1e6), "kernel_ms": ms.value}),
                   flush=True)
 
 
@@ -462,7 +732,9 @@ def parse():
     ap.add_argument("--accuracy-study", type=int, default=0, metavar="REALISATIONS",
                     help="instead of the benchmark line, run the Sec. 2.3.1 accuracy study "
                          "with this many realisations per (K, dt), oracle alongside")
-    ap.add_argument("--oracle-threads", type=int, default=16)
+    ap.add_argument("--oracle-threads", type=int, default=0,
+                    help="threads of the all-core oracle runs (0: one per CPU of the affinity "
+                         "mask, at most 16)")
     ap.add_argument("--next-rows", action="store_true",
                     help="time the Milstein, implicit and source-text model paths (one JSON "
                          "line per case)")
@@ -508,7 +780,8 @@ def main():
         paper_sweep(sode, torch, workloads, dev, args.paper_sweep)
         return
     if args.accuracy_study:
-        accuracy_study(sode, torch, workloads, dev, args.accuracy_study, args.oracle_threads)
+        accuracy_study(sode, torch, workloads, dev, args.accuracy_study,
+                       args.oracle_threads or host_threads()[1])
         return
     if args.next_rows:
         next_rows(sode, torch, dev)
@@ -563,26 +836,14 @@ def main():
     achieved = work["slots"] * orbits * nsteps / (kernel_ms * 1e-3)
     r_gpu = out[:, -1, 0].double().cpu().numpy()
 
-    plain_rate = mf_ms = None
+    fp64 = mf_ms = None
     r_mf = None
-    adj = rag = rnn = None
+    adj = rag = rnn = small = None
+    sample_rows = w["diagonal"][np.linspace(0, 255, args.cpu_orbits).astype(int)]
     if not args.grid_only:
-        # Plain FP64 one-orbit-per-lane kernel on the same ensemble (fewer steps;
-        # its per-step cost does not depend on the step count).
-        it64 = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=64, observable="kuramoto_r")
-        X64, p64 = X0.double(), p.double()
-        bsteps = args.baseline_steps
-        out64 = torch.empty((orbits, bsteps // stride + 1, 1), dtype=torch.float64, device=dev)
-        it64.integrate(X64[:256], p64[:256], 0.0, w["dt"], stride, stride, w["seed"])
-        torch.cuda.synchronize()
-        b0 = torch.cuda.Event(enable_timing=True)
-        b1 = torch.cuda.Event(enable_timing=True)
-        b0.record(stream)
-        it64.integrate(X64, p64, 0.0, w["dt"], bsteps, stride, w["seed"], out=out64)
-        b1.record(stream)
-        torch.cuda.synchronize()
-        plain_ms = b0.elapsed_time(b1)
-        plain_rate = orbits * bsteps / (plain_ms * 1e-3)
+        # Binary64 kernels on the same ensemble (fewer steps; their per-step
+        # cost does not depend on the step count).
+        fp64 = grid_fp64_leg(sode, torch, w, X0, p, dev, args.baseline_steps, sample_rows)
 
         # The same ensemble with the O(n) mean-field form of the coupling.
         itmf = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, observable="kuramoto_r",
@@ -600,15 +861,17 @@ def main():
         r_mf = outmf[:, -1, 0].double().cpu().numpy()
         itmf.close()
 
-        adj = adjoint_leg(sode, torch, workloads, dev)
-        rag = ragged_leg(sode, torch, workloads, dev)
-        rnn = rnn_leg(sode, torch, workloads, dev)
+        cpu_legs = not args.no_cpu
+        small = small_fp64_leg(sode, torch, workloads, dev, cpu=cpu_legs)
+        adj = adjoint_leg(sode, torch, workloads, dev, cpu=cpu_legs)
+        rag = ragged_leg(sode, torch, workloads, dev, cpu=cpu_legs)
+        rnn = rnn_leg(sode, torch, workloads, dev, cpu=cpu_legs)
 
     cpu = cpu_all = diag = None
     err = err_mf = err_all = None
     if not args.no_cpu:
         import oracle
-        rows = w["diagonal"][np.linspace(0, 255, args.cpu_orbits).astype(int)]
+        rows = sample_rows
         c0 = time.perf_counter()
         # The oracle gets the float32-rounded inputs the kernel received.
         X32 = w["X0"][rows].astype(np.float32).astype(np.float64)
@@ -628,7 +891,9 @@ def main():
             # Orbits are independent: one thread per core over disjoint shards
             # (the all-core CPU figure beside the single-core one).
             rows_all = w["diagonal"][np.linspace(0, 255, args.cpu_all_orbits).astype(int)]
-            nthreads = max(1, min(args.oracle_threads, os.cpu_count() or 1))
+            visible, nthreads = host_threads()
+            if args.oracle_threads:
+                nthreads = max(1, min(args.oracle_threads, visible))
             c0 = time.perf_counter()
             ref_all = oracle.integrate_parallel(
                 "kuramoto", n, n, 2 * n + 1, w["X0"][rows_all].astype(np.float32).astype(np.float64),
@@ -636,7 +901,7 @@ def main():
                 stride, w["seed"], threads=nthreads, orbit_ids=rows_all, observable="kuramoto_r")
             all_s = time.perf_counter() - c0
             cpu_all = {"value": len(rows_all) * nsteps / all_s, "unit": "orbit*steps/s",
-                       "cores": nthreads, "kind": "oracle",
+                       "cores": nthreads, "host_cpus_visible": visible, "kind": "oracle",
                        "sample": f"{len(rows_all)} grid-diagonal orbits x {nsteps} steps, FP64, "
                                  f"{nthreads} threads, {all_s:.1f} s"}
             dr_all = np.abs(r_gpu[rows_all] - ref_all[:, -1, 0])
@@ -683,14 +948,16 @@ def main():
                      "slots_per_orbit_step": work["slots"]},
         "cpu_baseline": cpu,
         "cpu_all_cores": cpu_all,
-        "plain_fp64": None if plain_rate is None else {
-            "value": plain_rate, "unit": "orbit*steps/s", "nsteps": args.baseline_steps,
-            "speedup_of_value": value / plain_rate},
+        "plain_fp64": None if fp64 is None else dict(
+            fp64["plain_fp64"], speedup_of_value=value / fp64["plain_fp64"]["value"]),
+        "lanes16_fp64": None if fp64 is None else dict(
+            fp64["lanes16_fp64"], speedup_of_value=value / fp64["lanes16_fp64"]["value"]),
         "error": {"max_abs_dr_final": err, "max_abs_dr_final_diagonal": err_all,
                   "tolerance": 1e-4, "diagonal": diag},
         "meanfield": None if mf_ms is None else {
             "value": orbits * nsteps / (mf_ms * 1e-3), "unit": "orbit*steps/s",
             "kernel_ms": mf_ms, "max_abs_dr_final": err_mf},
+        "small_fp64": small,
         "adjoint": adj,
         "ragged": rag,
         "rnn": rnn,

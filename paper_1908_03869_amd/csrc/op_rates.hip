@@ -12,14 +12,18 @@
 // one-instruction inline assembly, so the compiler neither drops nor
 // rewrites any of them.  Chains are independent of each other, so
 // consecutive instructions never wait on each other's results; DPP forms
-// read a register the loop never writes.  Lane 0 of every wave reads the
-// shader clock (clock64) before and after its loop; the host turns the
-// per-wave cycle counts into SIMD cycles per wave-instruction.  The binary64
-// library functions (sin, cos, log, sqrt of the device math library) are
-// timed the same way over dependent call chains, per call.
+// read a register the loop never writes.  One workgroup runs per CU with W
+// waves on each of its four SIMDs; after a barrier every wave reads the
+// shader clock (clock64) before and after its loop, and the host takes a
+// workgroup's span (latest end - earliest start) as the SIMD cycles its
+// W waves' instructions took: cycles per wave-instruction = span / (W x
+// instructions per wave).  W = 1 shows what one wave alone can issue, W = 4
+// what the SIMD can.  The binary64 library functions (sin, cos, log, sqrt
+// of the device math library) are timed the same way over dependent call
+// chains, per call.
 //
-// Only ALU work and one store per lane (to a buffer of one float per lane)
-// and one per wave (to a buffer of one 64-bit count per wave).
+// Only ALU work, one store per lane (to a buffer of one float per lane) and
+// two per wave (its two clock readings).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -50,6 +54,8 @@ enum Op : int {
     kMixSin1Fma3,   // one v_sin_f32 then three v_fma_f32 (4 instructions)
     kMixPair,       // v_sub_f32_dpp, v_sin_f32, two v_add_f32: one coupling pair
     kMixPairNoDpp,  // the same with a plain v_sub_f32
+    kMixFolded4,    // one partner phase against four own phases, the read folded into four v_sub_f32_dpp
+    kMixMov4,       // the same with one v_mov_b32_dpp and four plain v_sub_f32
     kLibSinF64,
     kLibCosF64,
     kLibLogF64,
@@ -63,14 +69,20 @@ const char* const kNames[kOpCount] = {
     "v_sin_f32", "v_log_f32", "v_sqrt_f32", "v_exp_f32", "v_rcp_f32", "v_mul_hi_u32",
     "v_mad_u64_u32", "v_bitop3_b32", "v_cvt_f32_u32", "v_rndne_f32", "v_fma_f64",
     "mix: v_sin_f32 + 3 v_fma_f32", "mix: coupling pair (sub_dpp, sin, 2 add)",
-    "mix: coupling pair without DPP (sub, sin, 2 add)", "binary64 sin (library call)",
+    "mix: coupling pair without DPP (sub, sin, 2 add)",
+    "mix: 4 pairs, partner read folded (4 sub_dpp, 4 sin, 8 add)",
+    "mix: 4 pairs, partner read once (mov_dpp, 4 sub, 4 sin, 8 add)", "binary64 sin (library call)",
     "binary64 cos (library call)", "binary64 log (library call)", "binary64 sqrt (library call)",
     "binary32 sinf (library call)"};
 
 // Instructions (or library calls) per chain per block.
-constexpr int per_block(int op)
+// Instructions (or library calls) per block of 8 chains.
+constexpr double per_block8(int op)
 {
-    return op == kMixSin1Fma3 || op == kMixPair || op == kMixPairNoDpp ? 4 : 1;
+    return op == kMixSin1Fma3 || op == kMixPair || op == kMixPairNoDpp ? 32.0
+           : op == kMixFolded4                                          ? 32.0
+           : op == kMixMov4                                             ? 34.0
+                                                                        : 8.0;
 }
 
 #define SODE_R8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
@@ -159,6 +171,35 @@ __device__ __forceinline__ void block_f32(float (&a)[kChains], float (&e)[kChain
 #define X(i) asm volatile("v_add_f32 %0, %1, %0" : "+v"(e[(i + 4) % 8]) : "v"(d[i]));
         SODE_R8(X)
 #undef X
+    } else if constexpr (OP == kMixFolded4 || OP == kMixMov4) {
+        // Pairs of one partner phase (read from the lane five rotations
+        // away) with the own phases a[0..3], then with a[4..7]: differences,
+        // sines, and the two accumulations of each sine, as the 16-lane
+        // coupling issues them.
+        float d[kChains];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if constexpr (OP == kMixFolded4) {
+#define X(i) asm volatile("v_sub_f32_dpp %0, %1, %2 row_ror:5 row_mask:0xf bank_mask:0xf" : "=v"(d[4 * h + i]) : "v"(b), "v"(a[4 * h + i]));
+                X(0) X(1) X(2) X(3)
+#undef X
+            } else {
+                float t;
+                asm volatile("v_mov_b32_dpp %0, %1 row_ror:5 row_mask:0xf bank_mask:0xf" : "=v"(t) : "v"(b));
+#define X(i) asm volatile("v_sub_f32 %0, %1, %2" : "=v"(d[4 * h + i]) : "v"(t), "v"(a[4 * h + i]));
+                X(0) X(1) X(2) X(3)
+#undef X
+            }
+#define X(i) asm volatile("v_sin_f32 %0, %0" : "+v"(d[4 * h + i]));
+            X(0) X(1) X(2) X(3)
+#undef X
+#define X(i) asm volatile("v_add_f32 %0, %1, %0" : "+v"(e[4 * h + i]) : "v"(d[4 * h + i]));
+            X(0) X(1) X(2) X(3)
+#undef X
+#define X(i) asm volatile("v_add_f32 %0, %1, %0" : "+v"(e[(4 * h + i + 4) % 8]) : "v"(d[4 * h + i]));
+            X(0) X(1) X(2) X(3)
+#undef X
+        }
     } else if constexpr (OP == kLibSinF32) {
 #define X(i) a[i] = sinf(a[i]) + b;
         SODE_R8(X)
@@ -217,9 +258,12 @@ constexpr bool is_f64(int op)
     return op == kFmaF64 || op == kLibSinF64 || op == kLibCosF64 || op == kLibLogF64 || op == kLibSqrtF64;
 }
 
-// out: one float per lane of the grid; cycles: one count per wave.
+// out: one float per lane of the grid; stamps: the shader-clock readings
+// (start, end) of each wave's loop.  All waves of a workgroup start the loop
+// together (after a barrier), so a workgroup's span is the SIMD time its
+// waves' instructions took on the CU's four SIMDs.
 template <int OP>
-__global__ void op_rate_kernel(float* __restrict__ out, unsigned long long* __restrict__ cycles, int iters,
+__global__ void op_rate_kernel(float* __restrict__ out, unsigned long long* __restrict__ stamps, int iters,
                                float seed)
 {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -240,6 +284,7 @@ __global__ void op_rate_kernel(float* __restrict__ out, unsigned long long* __re
     }
     const uint32_t v = 0xD2511F53u ^ (uint32_t)tid;
     const double y = 1e-3 * (double)b;
+    __syncthreads();
     const unsigned long long t0 = clock64();
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
@@ -259,8 +304,10 @@ __global__ void op_rate_kernel(float* __restrict__ out, unsigned long long* __re
         acc += a[i] + e[i] + (float)(u[i] ^ (uint32_t)w[i] ^ (uint32_t)(w[i] >> 32) ^ (uint32_t)cy[i]) +
                (float)x[i];
     out[tid] = acc;
-    if ((threadIdx.x & 63) == 0)
-        cycles[tid >> 6] = t1 - t0;
+    if ((threadIdx.x & 63) == 0) {
+        stamps[2 * (tid >> 6)] = t0;
+        stamps[2 * (tid >> 6) + 1] = t1;
+    }
 }
 
 using KernelFn = void (*)(float*, unsigned long long*, int, float);
@@ -292,17 +339,19 @@ double op_rates_ops_per_wave(int op, int iters)
 {
     if (op < 0 || op >= kOpCount)
         return 0.0;
-    return (double)iters * kRepeat * kChains * per_block(op);
+    return (double)iters * kRepeat * per_block8(op);
 }
 
-// Run op `op` over `blocks` blocks of `wave_per_block` waves (1..16).  On
-// success: *mean_cycles = mean over waves of the shader-clock cycles of the
-// loop, *ms = launch duration (HIP events).  Returns 0, or -1 for bad
+// Run op `op` over `blocks` workgroups of `waves_per_block` waves (4..16, a
+// multiple of 4: the same number of waves on each of a CU's four SIMDs).
+// Launch one workgroup per CU.  On success: *mean_cycles = mean over
+// workgroups of the span of their loops (latest end - earliest start, shader
+// clock), *ms = launch duration (HIP events).  Returns 0, or -1 for bad
 // arguments, -2 for a HIP error.
 int op_rates_run(int op, int blocks, int waves_per_block, int iters, double* mean_cycles, double* ms)
 {
-    if (op < 0 || op >= kOpCount || blocks < 1 || blocks > (1 << 16) || waves_per_block < 1 ||
-        waves_per_block > 16 || iters < 1 || !mean_cycles || !ms)
+    if (op < 0 || op >= kOpCount || blocks < 1 || blocks > (1 << 16) || waves_per_block < 4 ||
+        waves_per_block > 16 || waves_per_block % 4 != 0 || iters < 1 || !mean_cycles || !ms)
         return -1;
     const int threads = 64 * waves_per_block;
     const size_t lanes = (size_t)blocks * threads;
@@ -311,7 +360,7 @@ int op_rates_run(int op, int blocks, int waves_per_block, int iters, double* mea
     unsigned long long* cyc = nullptr;
     if (hipMalloc(&out, lanes * sizeof(float)) != hipSuccess)
         return -2;
-    if (hipMalloc(&cyc, waves * sizeof(unsigned long long)) != hipSuccess) {
+    if (hipMalloc(&cyc, 2 * waves * sizeof(unsigned long long)) != hipSuccess) {
         (void)hipFree(out);
         return -2;
     }
@@ -333,14 +382,21 @@ int op_rates_run(int op, int blocks, int waves_per_block, int iters, double* mea
         float t = 0.0f;
         (void)hipEventElapsedTime(&t, e0, e1);
         *ms = t;
-        unsigned long long* host = new unsigned long long[waves];
-        if (hipMemcpy(host, cyc, waves * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess) {
+        unsigned long long* host = new unsigned long long[2 * waves];
+        if (hipMemcpy(host, cyc, 2 * waves * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess) {
             rc = -2;
         } else {
             double s = 0.0;
-            for (size_t i = 0; i < waves; ++i)
-                s += (double)host[i];
-            *mean_cycles = s / (double)waves;
+            for (int blk = 0; blk < blocks; ++blk) {
+                unsigned long long lo = ~0ull, hi = 0;
+                for (int wv = 0; wv < waves_per_block; ++wv) {
+                    const size_t i = (size_t)blk * waves_per_block + wv;
+                    lo = host[2 * i] < lo ? host[2 * i] : lo;
+                    hi = host[2 * i + 1] > hi ? host[2 * i + 1] : hi;
+                }
+                s += (double)(hi - lo);
+            }
+            *mean_cycles = s / (double)blocks;
         }
         delete[] host;
     }

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <utility>
 #include <vector>
 
@@ -80,15 +81,17 @@ struct HostPlan {
     std::vector<int32_t> shape;  // [ngroups]
 };
 
-// Group instances of one lane shape (sorted by step count, longest first)
-// into groups of 64/L, then order all groups by decreasing U x steps.
+// Group instances of one lane shape and one save stride (sorted by step
+// count, longest first) into groups of 64/L, then order all groups by
+// decreasing U x steps.  A group's instances share the stride, so its wave
+// follows one save schedule.
 void build_plan(const sode_instance_t* inst, int32_t count, int units_min, HostPlan& plan)
 {
     struct Member {
         int64_t nsteps;
         int32_t idx;
     };
-    std::vector<Member> by_shape[kRaggedShapes];
+    std::map<std::pair<int, int64_t>, std::vector<Member>> buckets;  // (shape, stride)
     int lanes_of[kRaggedShapes] = {0}, units_of[kRaggedShapes] = {0};
     for (int32_t i = 0; i < count; ++i) {
         int L, U;
@@ -96,7 +99,7 @@ void build_plan(const sode_instance_t* inst, int32_t count, int units_min, HostP
         const int code = ragged_shape_code(L, U);
         lanes_of[code] = L;
         units_of[code] = U;
-        by_shape[code].push_back({inst[i].nsteps, i});
+        buckets[{code, inst[i].stride}].push_back({inst[i].nsteps, i});
     }
     struct Group {
         int64_t cost;
@@ -105,10 +108,9 @@ void build_plan(const sode_instance_t* inst, int32_t count, int units_min, HostP
         std::vector<int32_t> members;
     };
     std::vector<Group> groups;
-    for (int code = 0; code < kRaggedShapes; ++code) {
-        auto& v = by_shape[code];
-        if (v.empty())
-            continue;
+    for (auto& bucket : buckets) {
+        const int code = bucket.first.first;
+        auto& v = bucket.second;
         std::sort(v.begin(), v.end(), [](const Member& a, const Member& b) {
             return a.nsteps != b.nsteps ? a.nsteps > b.nsteps : a.idx < b.idx;
         });

@@ -38,3 +38,29 @@ def test_headline_workload_slot_count():
     import bench
     c = bench.algorithmic_slots_per_orbit_step(64)
     assert (c["valu"], c["trans"], c["imul"], c["slots"]) == (7296, 2144, 640, 17152)
+
+
+def test_fp64_work_counts_each_pair_once():
+    """The binary64 roofline's work for n = 4: six pair sines plus the sine and
+    cosine of two Box-Muller pairs, two logarithms and square roots, one
+    Philox block."""
+    import bench
+    c = bench.fp64_slots_per_orbit_step(4)
+    assert (c["sin"], c["log"], c["sqrt"], c["imul"], c["valu32"]) == (10, 2, 2, 20, 20)
+    assert c["fma64"] == 3 * 6 + 7 * 4 + 7 * 2
+    assert abs(c["slots"] - sum(c[k] * bench.FP64_SLOTS[k] for k in bench.FP64_SLOTS)) < 1e-9
+
+
+def test_stratified_sample_covers_the_grid():
+    """64 instances, one per (unit-count bin, step-count bin) cell where the
+    cell is occupied, distinct, and spanning the batch's extremes of both."""
+    import numpy as np
+    import bench
+    import workloads
+    w = workloads.fhn_ragged()
+    s = bench.stratified_instances(w["units"], w["nsteps"])
+    assert len(s) == 64 and len(set(s.tolist())) == 64
+    assert w["units"][s].min() <= np.quantile(w["units"], 0.05)
+    assert w["units"][s].max() >= np.quantile(w["units"], 0.9)
+    assert w["nsteps"][s].max() >= np.quantile(w["nsteps"], 0.9)
+    assert w["nsteps"][s].min() <= np.quantile(w["nsteps"], 0.05)

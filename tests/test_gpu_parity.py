@@ -350,7 +350,17 @@ def test_phase_convention_does_not_depend_on_the_kernel(gpu, precision):
         assert circular_diff(got, want).max() <= tol, kernel
     log(f"wrap=0 auto fp{precision}")
     cont = run_library(w, precision=precision, wrap=0)
-    assert np.abs(cont - want).max() <= tol
+    assert np.abs(cont).max() > math.pi + 1.0  # not reduced
+    if precision == 32:
+        # Continuous binary32 phases are not reduced, so every update rounds
+        # at the spacing of |theta| (up to 2^-19 here, against 2^-22 in
+        # [-pi, pi]) and the rounding error can add up step after step: at
+        # most half that spacing per step.
+        ulp = 2.0 ** (math.floor(math.log2(np.abs(want).max())) - 23)
+        tol = 1e-4 + w["nsteps"] * ulp / 2
+    err = np.abs(cont - want).max()
+    print(f"wrap=0 fp{precision}: max |dtheta| {err:.3e} (bound {tol:.3e})")
+    assert err <= tol
 
 
 def test_shared_params_equal_per_orbit_rows(gpu):

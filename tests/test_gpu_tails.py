@@ -72,9 +72,11 @@ def test_resume_inside_a_group(gpu, precision, n):
 @pytest.mark.parametrize("n", [16, 32])
 def test_adjoint_with_odd_checkpoint_interval(gpu, n):
     """Checkpoints every 7 steps, 63 steps from step_offset = 5, window
-    [10, 61]: the checkpoints equal integrate's states bitwise, R is within
-    1e-5 of the oracle's and the gradient within 1e-3 relative of the FP64
-    oracle adjoint (the adjoint workload's bound)."""
+    [10, 61]: without compensation the checkpoints equal integrate's states
+    bitwise; with it (the default) each checkpoint is what integrate gives
+    when restarted from the one before it; R is within 1e-5 of the oracle's
+    and the gradient within 1e-3 relative of the FP64 oracle adjoint (the
+    adjoint workload's bound)."""
     import torch
     import oracle
     import paper_1908_03869_amd as sode
@@ -83,15 +85,26 @@ def test_adjoint_with_odd_checkpoint_interval(gpu, n):
     nsteps, every, lo, hi, off = 63, 7, 10, 61, 5
     X0 = torch.tensor(np.ascontiguousarray(w["X0"]), dtype=torch.float32, device="cuda")
     p = torch.tensor(w["p"], dtype=torch.float32, device="cuda")
-    it = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, shared_params=1)
     args = (0.0, w["dt"], nsteps, every, lo, hi, w["seed"])
     log(f"tails adjoint n={n} every={every} offset={off}")
+    it0 = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, shared_params=1,
+                          compensated=0)
+    ckpt0, _ = it0.forward_ckpt(X0, p, *args, step_offset=off)
+    it0.sync()
+    states = run_library(dict(w, observable="state"), precision=32, kernel="coupled",
+                         nsteps=nsteps, stride=every, step_offset=off, shared=True,
+                         compensated=0)
+    np.testing.assert_array_equal(ckpt0.double().cpu().numpy(), states)
+    it = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=32, shared_params=1)
     ckpt, R = it.forward_ckpt(X0, p, *args, step_offset=off)
     grad, _ = it.adjoint(p, ckpt, *args, step_offset=off)
     it.sync()
-    states = run_library(dict(w, observable="state"), precision=32, kernel="coupled",
-                         nsteps=nsteps, stride=every, step_offset=off, shared=True)
-    np.testing.assert_array_equal(ckpt.double().cpu().numpy(), states)
+    ck = ckpt.double().cpu().numpy()
+    for c in range(ck.shape[1] - 1):
+        seg = run_library(dict(w, observable="state"), precision=32, kernel="coupled",
+                          X0=ck[:, c], nsteps=every, stride=every, step_offset=off + c * every,
+                          t0=c * every * w["dt"], shared=True)
+        np.testing.assert_array_equal(seg[:, -1], ck[:, c + 1], err_msg=f"checkpoint {c + 1}")
 
     Rref, gref, _ = oracle.kuramoto_adjoint(n, as_received(w["X0"], 32),
                                             as_received(w["p"], 32), 0.0, w["dt"], nsteps,
