@@ -58,7 +58,8 @@ enum sode_status {
     SODE_EDEVICE = -3,      /* a HIP call or a kernel launch failed             */
     SODE_EUNSUPPORTED = -4, /* valid request that this build does not implement */
     SODE_ENONFINITE = -5,   /* a saved state was NaN or infinite                */
-    SODE_EBUILD = -6        /* run-time compilation of a model source failed    */
+    SODE_EBUILD = -6,       /* run-time compilation of a model source failed    */
+    SODE_ETOOBIG = -7       /* request exceeds a fixed, library-owned capacity   */
 };
 
 /*
@@ -354,6 +355,26 @@ int sode_integrate_ragged(sode_t h, const sode_instance_t* inst, int32_t count, 
  */
 int sode_ensemble_stats(sode_t h, const void* out, int64_t orbits, int64_t cols, double* mean,
                         double* stddev, void* stream);
+
+/*
+ * sode_ensemble_stats_noalloc - sode_ensemble_stats for callers that cannot
+ * allocate device memory: code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, same kernels and the same
+ * bit-for-bit result, but the partials live in a fixed device array of the
+ * library (64 orbit chunks x SODE_STATS_NOALLOC_MAX_COLS columns x 24 bytes =
+ * 3 MiB per GPU, held until the process ends) instead of the handle's growable
+ * scratch, so the call never allocates device memory.
+ *   cols > SODE_STATS_NOALLOC_MAX_COLS -> SODE_ETOOBIG (before any HIP call).
+ * The first call on a device looks the array's address up on that device
+ * (a failure there -> SODE_EDEVICE).  Every call on one GPU shares that GPU's
+ * array: calls that may overlap on one GPU (different streams, or different
+ * host threads) race and must be serialised by the caller.  Nothing in the
+ * array needs clearing between calls: each call writes every partial it
+ * reads.
+ */
+#define SODE_STATS_NOALLOC_MAX_COLS 2048
+int sode_ensemble_stats_noalloc(sode_t h, const void* out, int64_t orbits, int64_t cols,
+                                double* mean, double* stddev, void* stream);
 
 /*
  * sode_sync - wait for the handle's last launch and report device errors.

@@ -174,8 +174,11 @@ class Integrator:
         check(st, "sode_integrate_ragged")
         return out
 
-    def ensemble_stats(self, out, stream=None):
-        """sode_ensemble_stats over out[orbits, ...]: (mean, std) float64 of shape out[0]."""
+    def ensemble_stats(self, out, stream=None, *, noalloc: bool = False):
+        """sode_ensemble_stats over out[orbits, ...]: (mean, std) float64 of shape out[0].
+        noalloc=True calls sode_ensemble_stats_noalloc (fixed library scratch,
+        at most SODE_STATS_NOALLOC_MAX_COLS columns; mean and std are still
+        allocated here by torch)."""
         import torch
         orbits = out.shape[0]
         cols = out[0].numel() if orbits > 0 else 0
@@ -185,9 +188,9 @@ class Integrator:
         std = torch.empty(out.shape[1:], dtype=torch.float64, device=out.device)
         if stream is None:
             stream = torch.cuda.current_stream(out.device).cuda_stream
-        st = abi.sode_ensemble_stats(self.handle, out.data_ptr(), orbits, cols, mean.data_ptr(),
-                                     std.data_ptr(), stream)
-        check(st, "sode_ensemble_stats")
+        fn = abi.sode_ensemble_stats_noalloc if noalloc else abi.sode_ensemble_stats
+        st = fn(self.handle, out.data_ptr(), orbits, cols, mean.data_ptr(), std.data_ptr(), stream)
+        check(st, fn.__name__)
         return mean, std
 
     def get_option(self, key: str) -> int:

@@ -20,13 +20,16 @@ SODE_EDEVICE = -3
 SODE_EUNSUPPORTED = -4
 SODE_ENONFINITE = -5
 SODE_EBUILD = -6
+SODE_ETOOBIG = -7
+# Column limit of sode_ensemble_stats_noalloc (its fixed device scratch).
+SODE_STATS_NOALLOC_MAX_COLS = 2048
 
 # Every symbol include/sode.h declares.
 EXPORTS = (
     "sode_create", "sode_create_custom", "sode_build", "sode_build_log",
     "sode_set_option", "sode_get_option", "sode_integrate",
     "sode_integrate_ex", "sode_forward_ckpt", "sode_adjoint", "sode_integrate_ragged",
-    "sode_ensemble_stats", "sode_sync", "sode_destroy", "sode_strerror", "sode_version",
+    "sode_ensemble_stats", "sode_ensemble_stats_noalloc", "sode_sync", "sode_destroy", "sode_strerror", "sode_version",
 )
 
 
@@ -92,6 +95,8 @@ def load() -> ctypes.CDLL:
     L.sode_integrate_ragged.restype = ctypes.c_int
     L.sode_ensemble_stats.argtypes = [vp, vp, i64, i64, vp, vp, vp]
     L.sode_ensemble_stats.restype = ctypes.c_int
+    L.sode_ensemble_stats_noalloc.argtypes = [vp, vp, i64, i64, vp, vp, vp]
+    L.sode_ensemble_stats_noalloc.restype = ctypes.c_int
     L.sode_sync.argtypes = [vp]
     L.sode_sync.restype = ctypes.c_int
     L.sode_destroy.argtypes = [vp]
@@ -176,6 +181,10 @@ def sode_integrate_ragged(h, inst, count, X0, x0_len, p, p_len, out, out_len, t0
 
 def sode_ensemble_stats(h, out, orbits, cols, mean, stddev, stream) -> int:
     return load().sode_ensemble_stats(h, out, orbits, cols, mean, stddev, stream)
+
+
+def sode_ensemble_stats_noalloc(h, out, orbits, cols, mean, stddev, stream) -> int:
+    return load().sode_ensemble_stats_noalloc(h, out, orbits, cols, mean, stddev, stream)
 
 
 def sode_sync(h) -> int:

@@ -110,6 +110,13 @@ struct StatsRequest {
 };
 size_t stats_partial_bytes();
 hipError_t launch_ensemble_stats(const StatsRequest& r);
+// The non-allocating variant's fixed device scratch: kStatsStaticPartials
+// partials (64 orbit chunks x SODE_STATS_NOALLOC_MAX_COLS columns).  Returns
+// the current device's address of it (looked up once per device), or
+// nullptr with *err set.
+constexpr int64_t kStatsChunks = 64;
+constexpr int64_t kStatsStaticPartials = kStatsChunks * SODE_STATS_NOALLOC_MAX_COLS;
+void* stats_static_scratch(hipError_t* err);
 
 // Dense random networks with the drift's matrix product on MFMA (binary32
 // state, shared parameters, n in {64, 128, 256}).

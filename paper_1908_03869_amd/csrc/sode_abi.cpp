@@ -196,6 +196,7 @@ const char* sode_strerror(int status)
     case SODE_EUNSUPPORTED: return "unsupported combination of model, size and options";
     case SODE_ENONFINITE: return "non-finite value in a saved state";
     case SODE_EBUILD: return "run-time compilation of the model source failed (see sode_build_log)";
+    case SODE_ETOOBIG: return "request exceeds the fixed capacity of a non-allocating entry point";
     default: return "unknown status";
     }
 }
@@ -578,41 +579,89 @@ int sode_adjoint(sode_t h, const void* p, int64_t orbits, double t0, double dt, 
     return status_of(e);
 }
 
-int sode_ensemble_stats(sode_t h, const void* out, int64_t orbits, int64_t cols, double* mean,
-                        double* stddev, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Argument checks and orbit partition shared by both statistics entry
+// points.  SODE_OK with *empty set when there is nothing to compute.
+int stats_request(sode_t h, const void* out, int64_t orbits, int64_t cols, double* mean,
+                  double* stddev, void* stream, sode::StatsRequest* r, bool* empty)
 {
+    *empty = false;
     if (!h || orbits < 0 || cols < 0)
         return SODE_EINVAL;
-    if (cols == 0)
+    if (cols == 0) {
+        *empty = true;
         return SODE_OK;
+    }
     if (!mean || (orbits > 0 && !out))
         return SODE_EINVAL;
     if (orbits > 0 && cols > INT64_MAX / 16 / orbits)
         return SODE_EINVAL;
     if ((cols + 255) / 256 > INT32_MAX)
         return SODE_EINVAL;
-    sode::StatsRequest r{};
-    r.x = out;
-    r.precision = h->precision;
-    r.orbits = orbits;
-    r.cols = cols;
+    *r = sode::StatsRequest{};
+    r->x = out;
+    r->precision = h->precision;
+    r->orbits = orbits;
+    r->cols = cols;
     // About 64 orbit chunks, fewer for small ensembles.
-    r.groups = orbits < 64 ? (orbits > 0 ? orbits : 1) : 64;
-    r.chunk = orbits > 0 ? (orbits + r.groups - 1) / r.groups : 1;
-    r.groups = orbits > 0 ? (orbits + r.chunk - 1) / r.chunk : 1;
-    const size_t need = (size_t)r.groups * (size_t)cols * sode::stats_partial_bytes();
-    const int sc = ensure_scratch(h, need);
-    if (sc != SODE_OK)
-        return sc;
-    r.scratch = h->scratch;
-    r.mean = mean;
-    r.stddev = stddev;
-    r.stream = static_cast<hipStream_t>(stream);
+    r->groups = orbits < sode::kStatsChunks ? (orbits > 0 ? orbits : 1) : sode::kStatsChunks;
+    r->chunk = orbits > 0 ? (orbits + r->groups - 1) / r->groups : 1;
+    r->groups = orbits > 0 ? (orbits + r->chunk - 1) / r->chunk : 1;
+    r->mean = mean;
+    r->stddev = stddev;
+    r->stream = static_cast<hipStream_t>(stream);
+    return SODE_OK;
+}
+
+int stats_launch(sode_t h, const sode::StatsRequest& r)
+{
     const hipError_t e = sode::launch_ensemble_stats(r);
     h->last_error = e;
     h->last_stream = r.stream;
     h->launched = true;
     return status_of(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sode_ensemble_stats(sode_t h, const void* out, int64_t orbits, int64_t cols, double* mean,
+                        double* stddev, void* stream)
+{
+    sode::StatsRequest r;
+    bool empty = false;
+    const int st = stats_request(h, out, orbits, cols, mean, stddev, stream, &r, &empty);
+    if (st != SODE_OK || empty)
+        return st;
+    const size_t need = (size_t)r.groups * (size_t)cols * sode::stats_partial_bytes();
+    const int sc = ensure_scratch(h, need);
+    if (sc != SODE_OK)
+        return sc;
+    r.scratch = h->scratch;
+    return stats_launch(h, r);
+}
+
+int sode_ensemble_stats_noalloc(sode_t h, const void* out, int64_t orbits, int64_t cols,
+                                double* mean, double* stddev, void* stream)
+{
+    sode::StatsRequest r;
+    bool empty = false;
+    const int st = stats_request(h, out, orbits, cols, mean, stddev, stream, &r, &empty);
+    if (st != SODE_OK || empty)
+        return st;
+    if (cols > SODE_STATS_NOALLOC_MAX_COLS)
+        return SODE_ETOOBIG;
+    hipError_t e = hipSuccess;
+    r.scratch = sode::stats_static_scratch(&e);
+    if (!r.scratch) {
+        h->last_error = e;
+        return SODE_EDEVICE;
+    }
+    return stats_launch(h, r);
 }
 
 int sode_destroy(sode_t h)

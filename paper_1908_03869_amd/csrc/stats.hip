@@ -10,6 +10,8 @@
 // consecutive threads on consecutive columns so every read is coalesced);
 // (2) one thread per column merges the chunks in order with the pairwise
 // combination of Chan, Golub & LeVeque.
+#include <mutex>
+
 #include "launch.hpp"
 
 namespace sode {
@@ -18,6 +20,15 @@ namespace {
 struct Partial {
     double n, mean, m2;
 };
+
+// Fixed device scratch of the non-allocating entry point: room for the
+// partials of kStatsStaticPartials (orbit chunk, column) pairs, 3 MiB.  Each
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes this name to a kernel (on the host it is a stand-in, not
+// a device address); it uses the address stats_static_scratch() looks up.
+static __device__ __align__(256) Partial scratch[kStatsStaticPartials];
+
+constexpr int kMaxDevices = 64;
 
 template <typename R>
 __global__ __launch_bounds__(256) void column_partials(const R* __restrict__ x, int64_t orbits, int64_t cols,
@@ -80,6 +91,33 @@ hipError_t launch_typed(const StatsRequest& r)
 }  // namespace
 
 size_t stats_partial_bytes() { return sizeof(Partial); }
+
+void* stats_static_scratch(hipError_t* err)
+{
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= kMaxDevices))
+        e = hipErrorInvalidDevice;
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // With device `dev` current: its own copy of the array.
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        addr[dev] = ptr;
+    }
+    *err = hipSuccess;
+    return addr[dev];
+}
 
 hipError_t launch_ensemble_stats(const StatsRequest& r)
 {

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_strerror_covers_every_status():
-    for st in (0, -1, -2, -3, -4, -5):
+    for st in (0, -1, -2, -3, -4, -5, -6, -7):
         assert abi.sode_strerror(st) and abi.sode_strerror(st) != "unknown status"
     assert abi.sode_strerror(-99) == "unknown status"
 
@@ -341,3 +341,27 @@ def test_ensemble_stats_argument_checks():
     assert abi.sode_ensemble_stats(h, FAKE, 10, 0, None, None, None) == abi.SODE_OK
     assert abi.sode_ensemble_stats(None, FAKE, 10, 10, FAKE, None, None) == abi.SODE_EINVAL
     abi.sode_destroy(h)
+
+
+def test_ensemble_stats_noalloc_argument_checks():
+    """Same checks as sode_ensemble_stats, plus the fixed capacity: more than
+    SODE_STATS_NOALLOC_MAX_COLS columns is refused before any HIP call."""
+    st, h = abi.sode_create("kuramoto", 4, 4, 9)
+    f = abi.sode_ensemble_stats_noalloc
+    assert f(h, FAKE, -1, 10, FAKE, None, None) == abi.SODE_EINVAL
+    assert f(h, FAKE, 10, -1, FAKE, None, None) == abi.SODE_EINVAL
+    assert f(h, None, 10, 10, FAKE, None, None) == abi.SODE_EINVAL
+    assert f(h, FAKE, 10, 10, None, None, None) == abi.SODE_EINVAL
+    assert f(h, FAKE, 10, 0, None, None, None) == abi.SODE_OK
+    assert f(None, FAKE, 10, 10, FAKE, None, None) == abi.SODE_EINVAL
+    big = abi.SODE_STATS_NOALLOC_MAX_COLS + 1
+    assert f(h, FAKE, 10, big, FAKE, None, None) == abi.SODE_ETOOBIG
+    assert f(h, FAKE, 1 << 20, big, FAKE, FAKE, None) == abi.SODE_ETOOBIG
+    assert "fixed capacity" in abi.sode_strerror(abi.SODE_ETOOBIG)
+    abi.sode_destroy(h)
+
+
+def test_noalloc_column_limit_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define SODE_STATS_NOALLOC_MAX_COLS (\d+)", text)
+    assert m and int(m.group(1)) == abi.SODE_STATS_NOALLOC_MAX_COLS
