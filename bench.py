@@ -373,8 +373,9 @@ def small_fp64_leg(sode, torch, workloads, dev, reps: int = 5, cpu: bool = True)
     """The n = 4 binary64 ensemble: 1024 orbits (32 coupling values x 32
     seeds, the orbits of one seed sharing its Brownian path), dt = 1e-3,
     10^4 steps, state saved every 100 steps.  Kernel time (HIP events, median
-    of `reps` after a warm-up) on the automatically chosen kernel (16 lanes
-    per orbit) and on one orbit per lane; error = max circular |dtheta| over
+    of `reps` after a warm-up) on the automatically chosen kernel (the
+    coupled kernel's four-lane form: one oscillator per lane, DPP quad
+    permutations) and on one orbit per lane; error = max circular |dtheta| over
     all 1024 orbits and saves against the FP64 oracle (bound 1e-10), which
     is also timed single-threaded on all of them.
 
@@ -383,8 +384,8 @@ def small_fp64_leg(sode, torch, workloads, dev, reps: int = 5, cpu: bool = True)
     the per-pair and per-oscillator arithmetic, one Philox block), each
     class priced in binary64 FMA issue slots by its measured cost, against
     the chip's 256 x 4 x 16 x 2.4e9 = 3.93e13 binary64 FMA lane-slots/s
-    (78.6 TFLOP/s).  1024 orbits are 16 waves on one lane each, or 256 on
-    16 lanes: far fewer than the chip's 1024 SIMDs, so the fraction also
+    (78.6 TFLOP/s).  1024 orbits are 16 waves on one lane each, or 64 on
+    four lanes: far fewer than the chip's 1024 SIMDs, so the fraction also
     says how much of the chip this small ensemble can occupy."""
     w = workloads.kuramoto_small()
     n, orbits, nsteps, stride = w["n"], w["X0"].shape[0], w["nsteps"], w["stride"]
@@ -412,13 +413,13 @@ def small_fp64_leg(sode, torch, workloads, dev, reps: int = 5, cpu: bool = True)
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
         ms = float(np.median(times))
-        name = "lanes16" if kernel == "auto" else "plain"
+        name = "coupled" if kernel == "auto" else "plain"
         res[name] = {"kernel_ms": ms, "orbit_steps_per_s": orbits * nsteps / (ms * 1e-3),
                      "us_per_step": ms * 1e3 / nsteps}
         outs[name] = out.cpu().numpy()
         it.close()
     work = fp64_slots_per_orbit_step(n)
-    for name in ("lanes16", "plain"):
+    for name in ("coupled", "plain"):
         achieved = work["slots"] * orbits * nsteps / (res[name]["kernel_ms"] * 1e-3)
         res[name]["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
                                  "peak": FP64_FMA_SLOTS_PER_S / 1e12,
@@ -435,7 +436,7 @@ def small_fp64_leg(sode, torch, workloads, dev, reps: int = 5, cpu: bool = True)
                                "kind": "oracle",
                                "sample": f"all {orbits} orbits x {nsteps} steps, FP64, "
                                          f"single-threaded, {cs:.1f} s"}
-        for name in ("lanes16", "plain"):
+        for name in ("coupled", "plain"):
             d = np.abs(np.remainder(outs[name] - ref + math.pi, 2 * math.pi) - math.pi)
             res[name]["error"] = {"max_circular_dtheta": float(d.max()), "tolerance": 1e-10}
     return res

@@ -179,13 +179,15 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  orbit exchange phases
  *                  through DPP row rotations; an n that is not a multiple
  *                  of 16 runs padded with oscillators frozen at phase 0
- *                  whose coupling is cancelled); 3 = matrix (see "gemm").
+ *                  whose coupling is cancelled; binary64 with n <= 4 uses
+ *                  4 lanes per orbit and DPP quad permutations instead);
+ *                  3 = matrix (see "gemm").
  *                  Auto takes coupled for binary32 Kuramoto EM with
  *                  5 <= n <= 128 (n < 5: only up to 65,536 orbits) and for
- *                  binary64 Kuramoto EM with n <= 16 where it is faster
- *                  (n >= 10, else up to 400 n^2 orbits pairwise or 65,536
- *                  orbits mean-field), matrix for a supported dense
- *                  network, else plain.
+ *                  binary64 Kuramoto EM with n <= 4 at any size or
+ *                  5 <= n <= 16 where it is faster (n >= 10, else up to
+ *                  400 n^2 orbits pairwise or 65,536 orbits mean-field),
+ *                  matrix for a supported dense network, else plain.
  *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
  *                  used by every orbit.
  *   "gemm"         matrix kernel (model "rnn", precision 32, method EM,

@@ -328,6 +328,122 @@ __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64
     }
 }
 
+// A binary64 value held by another lane of the same quad, selected by the
+// DPP quad_perm control CTRL (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double quad_perm64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// quad_perm selections (lane i of a quad takes lane sel[i]):
+constexpr int kQuadNext = 0x39;  // [1, 2, 3, 0]: lane (l + 1) mod 4
+constexpr int kQuadPrev = 0x93;  // [3, 0, 1, 2]: lane (l - 1) mod 4
+constexpr int kQuadOpp = 0x4E;   // [2, 3, 0, 1]: lane (l + 2) mod 4
+
+__device__ __forceinline__ double quad_sum64(double v)
+{
+    v += quad_perm64<kQuadOpp>(v);
+    return v + quad_perm64<kQuadNext>(v);
+}
+
+// n <= 4: one orbit per quad of lanes, one oscillator per lane (lanes
+// l >= n hold pads at phase 0, cancelled as in the 16-lane kernel).  Every
+// unordered pair is evaluated once: the pairs (l, l + 1 mod 4) by lane l,
+// which returns the negated sine to lane l + 1, and the pairs (l, l + 2
+// mod 4) by both of their lanes.  Two binary64 sines per lane and step
+// instead of the 16-lane row's eight (and 16 lanes per orbit instead of 4).
+// The normals are lane_normals64_steps<1>: the quad is the orbit.
+template <bool PAD, bool MF>
+__global__ __launch_bounds__(256) void kuramoto_quad64_kernel(const Coupled64Args a)
+{
+    const int l = threadIdx.x & 3;
+    const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    // Whole quads are in or out together, so no quad_perm reads a finished lane.
+    if (o >= a.orbits)
+        return;
+    const int n = PAD ? a.n : 4;
+    const double* __restrict__ p = a.p + (a.p_per_orbit ? o * (int64_t)(2 * n + 1) : 0);
+    const int q = a.observable == kKuramotoR ? 1 : n;
+    double* __restrict__ out_row = a.out + o * a.nsave * q;
+
+    const bool real = !PAD || l < n;
+    double th = real ? load_phase64(a.X0[o * n + l]) : 0.0;
+    const double drift0 = real ? p[1 + l] * a.dt : 0.0;
+    const double noise = real ? p[1 + n + l] * a.sqdt : 0.0;
+    const double kc = real ? p[0] * (a.dt / (double)n) : 0.0;
+    const double w = real ? 1.0 : 0.0;
+    const double pads = (double)(4 - n);
+    const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
+
+    auto save = [&](int64_t s) {
+        if (a.observable == kKuramotoR) {
+            const double C = quad_sum64(cos(th) * w), S = quad_sum64(sin(th) * w);
+            const double r = sqrt(C * C + S * S) / (double)n;
+            if (l == 0) {
+                note_nonfinite(a.nonfinite, r);
+                out_row[s] = r;
+            }
+        } else if (real) {
+            note_nonfinite(a.nonfinite, th);
+            out_row[s * n + l] = th;
+        }
+    };
+
+    auto step = [&](double xi) {
+        double acc;
+        if constexpr (MF) {
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            const double C = quad_sum64(cs * w), S = quad_sum64(sn * w);
+            acc = cs * S - sn * C;
+        } else {
+            const double s1 = sin(quad_perm64<kQuadNext>(th) - th);
+            acc = s1 - quad_perm64<kQuadPrev>(s1);
+            acc += sin(quad_perm64<kQuadOpp>(th) - th);
+            if constexpr (PAD)
+                acc = fma(pads, sin(th), acc);
+        }
+        th = wrap64(th + (fma(kc, acc, drift0) + noise * xi));
+    };
+
+    save(0);
+    uint32_t k = (uint32_t)a.step_offset;
+    const int64_t nsteps = (a.nsave - 1) * a.stride;
+    int64_t s = 1, to_save = a.stride;
+    for (int64_t j = 0; j < nsteps; j += 4) {
+        double xb[4][1];
+        lane_normals64_steps<1>(st, k, l, xb);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t == 0 || j + t < nsteps) {
+                step(xb[t][0]);
+                ++k;
+                if (--to_save == 0) {
+                    save(s);
+                    ++s;
+                    to_save = a.stride;
+                }
+            }
+        }
+    }
+}
+
+template <bool PAD>
+hipError_t launch_quad64(const Request& r, const Coupled64Args& a)
+{
+    const int64_t threads = r.orbits * 4;
+    const dim3 block(256);
+    const dim3 grid((unsigned)((threads + 255) / 256));
+    if (r.drift == 1)
+        hipLaunchKernelGGL((kuramoto_quad64_kernel<PAD, true>), grid, block, 0, r.stream, a);
+    else
+        hipLaunchKernelGGL((kuramoto_quad64_kernel<PAD, false>), grid, block, 0, r.stream, a);
+    return hipGetLastError();
+}
+
 template <int P, bool PAD>
 hipError_t launch_p64(const Request& r)
 {
@@ -349,6 +465,8 @@ hipError_t launch_p64(const Request& r)
     a.orbit_offset = r.orbit_offset;
     a.step_offset = r.step_offset;
     a.nonfinite = r.nonfinite;
+    if (P == 1 && r.n <= 4)  // four lanes per orbit
+        return r.n == 4 ? launch_quad64<false>(r, a) : launch_quad64<true>(r, a);
     const int64_t threads = r.orbits * 16;
     const dim3 block(256);
     const dim3 grid((unsigned)((threads + 255) / 256));

@@ -99,11 +99,13 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
 // it applies, except for fewer than 5 oscillators over many orbits, where a
 // padded row wastes most of its lanes and one orbit per lane fills the chip
 // anyway (at n = 5 the 16-lane row is faster at every size measured).
-// Binary64, n <= 16: the 16-lane kernel from n = 10 at any size and below
-// that up to 400 n^2 orbits pairwise (one orbit per lane costs ~n^2 per
-// orbit-step, the padded row a constant; crossover between 5,120 and 25,600
-// orbits at n = 5) or 65,536 orbits mean-field (crossover between 40,960
-// and 81,920 at n = 5); otherwise one orbit per lane.
+// Binary64, n <= 4: the four-lane form of the coupled kernel at any size (2
+// sines per lane-step, 8 per orbit-step against the 16 of one orbit per
+// lane).  Binary64, 5 <= n <= 16: the 16-lane kernel from n = 10 at any size
+// and below that up to 400 n^2 orbits pairwise (one orbit per lane costs
+// ~n^2 per orbit-step, the padded row a constant; crossover between 5,120 and
+// 25,600 orbits at n = 5) or 65,536 orbits mean-field (crossover between
+// 40,960 and 81,920 at n = 5); otherwise one orbit per lane.
 int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 {
     // RK4 and the implicit steppers integrate the ODE limit g = 0.  A model
@@ -146,8 +148,9 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
         *kernel = 1;
     } else if (coupled_ok && h->precision == 32 && (h->n >= 5 || orbits <= 65536)) {
         *kernel = 2;
-    } else if (coupled_ok && h->precision == 64 && h->n <= 16 &&
-               (h->n >= 10 || (h->drift == 1 ? orbits <= 65536 : orbits <= 400 * (int64_t)h->n * h->n))) {
+    } else if (coupled_ok && h->precision == 64 &&
+               (h->n <= 4 || (h->n <= 16 && (h->n >= 10 || (h->drift == 1 ? orbits <= 65536
+                                                                         : orbits <= 400 * (int64_t)h->n * h->n))))) {
         *kernel = 2;
     } else if (matrix_ok) {
         *kernel = 3;

@@ -1,5 +1,5 @@
-"""Binary64 16-lane Kuramoto kernel (kernel "coupled", precision 64) against
-the FP64 oracle.  The kernel evaluates each unordered pair once and sums in
+"""Binary64 coupled Kuramoto kernel (kernel "coupled", precision 64: 16 lanes
+per orbit, or 4 lanes per orbit for n <= 4) against the FP64 oracle.  The kernel evaluates each unordered pair once and sums in
 a different order than the oracle's index-order loops, so the comparison is
 to 1e-10 (the bound of the binary64 small-ensemble workload) rather than
 bitwise; phases are compared on the circle (the kernel wraps them)."""
@@ -40,3 +40,44 @@ def test_larger_rows(gpu, n):
     got = run_library(w, precision=64, kernel="coupled")
     want = run_oracle(w)
     assert np.abs(got - want).max() <= 1e-10
+
+
+@pytest.mark.parametrize("drift", [0, 1])
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_quad_form_small_systems(gpu, n, drift):
+    """n <= 4 runs four lanes per orbit (pads for n < 4), state and r saves,
+    with an orbit count that leaves a partial workgroup (77 orbits) and a
+    step count that is not a multiple of the four-step noise group."""
+    rng = np.random.default_rng(40 + n)
+    orbits = 77
+    X0 = rng.uniform(-np.pi, np.pi, (orbits, n))
+    p = workloads.kuramoto_params(rng.uniform(0.0, 4.0, orbits), rng.standard_normal((orbits, n)),
+                                  rng.uniform(0.05, 0.5, (orbits, n)))
+    for obs in ("state", "kuramoto_r"):
+        w = dict(model="kuramoto", n=n, m=n, d=2 * n + 1, X0=X0, p=p, t0=0.0, dt=1e-2, nsteps=1001,
+                 stride=143, seed=77, observable=obs)
+        log(f"coupled fp64 quad n={n} drift={drift} {obs}")
+        got = run_library(w, precision=64, kernel="coupled", drift=drift)
+        want = run_oracle(w)
+        d = circular_diff(got, want) if obs == "state" else np.abs(got - want)
+        assert d.max() <= 1e-10, d.max()
+
+
+def test_quad_form_auto_selection_and_shards(gpu):
+    """Auto selection takes the four-lane form for n = 4 in binary64 (same
+    bits as kernel "coupled"), and two shards by orbit_offset reproduce one
+    call bit for bit."""
+    w = workloads.kuramoto_small()
+    sel = slice(0, 130)
+    w = dict(w, X0=w["X0"][sel], p=w["p"][sel], orbit_ids=w["orbit_ids"][sel],
+             orbit_seeds=w["orbit_seeds"][sel], nsteps=500)
+    log("coupled fp64 quad auto vs coupled")
+    a = run_library(w, precision=64, kernel="coupled")
+    b = run_library(w, precision=64, kernel="auto")
+    np.testing.assert_array_equal(a, b)
+    w2 = dict(w, orbit_ids=None, orbit_seeds=None)
+    full = run_library(w2, precision=64, kernel="coupled")
+    lo = run_library(dict(w2, X0=w2["X0"][:50], p=w2["p"][:50]), precision=64, kernel="coupled")
+    hi = run_library(dict(w2, X0=w2["X0"][50:], p=w2["p"][50:]), precision=64, kernel="coupled",
+                     orbit_offset=50)
+    np.testing.assert_array_equal(np.concatenate([lo, hi]), full)
