@@ -29,9 +29,6 @@
 // compensation the forward pass carries each phase as hi + lo between
 // checkpoints and restarts lo at 0 after writing one, exactly as a segment
 // of the reverse pass starts from the stored hi.
-// lambda is binary32 carried as hi + lo (two-sum updates), so its rounding
-// does not random-walk over the 10^4 reverse steps of the gradient workload
-// (~6e-8 relative per step, ~6e-6 over the run without it).
 // Parameter gradients are accumulated per lane in binary64; per-orbit rows
 // are summed over orbits in binary64 in a fixed order, so the result does
 // not depend on scheduling.
@@ -140,38 +137,19 @@ __global__ __launch_bounds__(256) void forward_ckpt_kernel(const CkptArgs a)
         a.R[o] = racc * a.inv_window;
 }
 
-// Scale of w grad r(X) = scale (S cos X_j - C sin X_j), from the row sums
-// C, S; 0 where r vanishes (grad r is undefined there).
-template <int P>
-__device__ __forceinline__ float window_seed_scale(float C, float S, float w)
-{
-    constexpr float kInvN = 1.0f / (float)(16 * P);
-    const float z = __builtin_sqrtf(C * C + S * S);
-    return z >= 1e-30f ? w * kInvN / z : 0.0f;
-}
-
-// lambda += w grad r(X) on a plain binary32 lambda (the terminal seed).
+// lambda += w grad r(X), from the row sums C, S and the lane's cos/sin.
 template <int P>
 __device__ __forceinline__ void add_window_seed(float (&lam)[P], const float (&cs)[P], const float (&sn)[P],
                                                 float C, float S, float w)
 {
-    const float scale = window_seed_scale<P>(C, S, w);
+    constexpr float kInvN = 1.0f / (float)(16 * P);
+    const float z = __builtin_sqrtf(C * C + S * S);
+    if (z >= 1e-30f) {
+        const float scale = w * kInvN / z;
 #pragma unroll
-    for (int i = 0; i < P; ++i)
-        lam[i] += scale * (S * cs[i] - C * sn[i]);
-}
-
-// hi + lo += inc with Knuth's branch-free two-sum: the rounding error of
-// every update of the adjoint goes into lo, whatever the signs and sizes
-// (lambda changes sign and passes through zero), so it does not build up
-// over the 10^4 updates a component receives.
-__device__ __forceinline__ void two_sum_add(float& hi, float& lo, float inc)
-{
-    const float y = inc + lo;
-    const float s = hi + y;
-    const float bb = s - hi;
-    lo = (hi - (s - bb)) + (y - bb);
-    hi = s;
+        for (int i = 0; i < P; ++i)
+            lam[i] += scale * (S * cs[i] - C * sn[i]);
+    }
 }
 
 // Sum of a binary64 value over the 16 lanes of a row.
@@ -202,14 +180,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjointArgs a)
     float* __restrict__ seg = a.seg + (o * a.every * 16 + l) * (2 * P);
     const int64_t nsteps = (a.nckpt - 1) * a.every;
 
-    // lambda as the unevaluated sum lam + lam_lo (two_sum_add); the
-    // products use lam.
-    float lam[P], lam_lo[P];
+    float lam[P];
     double gK = 0.0, gW[P], gS[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         lam[i] = 0.0f;
-        lam_lo[i] = 0.0f;
         gW[i] = 0.0;
         gS[i] = 0.0;
     }
@@ -300,12 +275,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const AdjointArgs a)
             }
             gK += (double)kpart;
             const float A = row_sum(la), B = row_sum(lb);
-            const float seed = in_window(k, a.win_lo, a.win_hi) ? window_seed_scale<P>(C, S, a.inv_window) : 0.0f;
 #pragma unroll
-            for (int i = 0; i < P; ++i) {
-                const float jt = c.kc[0] * (cs[i] * A + sn[i] * B - lam[i] * (cs[i] * C + sn[i] * S));
-                two_sum_add(lam[i], lam_lo[i], jt + seed * (S * cs[i] - C * sn[i]));
-            }
+            for (int i = 0; i < P; ++i)
+                lam[i] += c.kc[0] * (cs[i] * A + sn[i] * B - lam[i] * (cs[i] * C + sn[i] * S));
+            if (in_window(k, a.win_lo, a.win_hi))
+                add_window_seed<P>(lam, cs, sn, C, S, a.inv_window);
         }
     }
 
