@@ -60,8 +60,12 @@ FP64_FMA_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 # wave64 issue cycles of each divided by those of one v_fma_f64 (the op-rate
 # microbenchmark, bench.py --op-rates, four waves per SIMD: sin/cos 258.7,
 # log 360.8, sqrt 88.6, v_mad_u64_u32 4.66, v_bitop3_b32 3.04 cycles against
-# 4.30 for v_fma_f64).
-FP64_SLOTS = {"sin": 60.2, "log": 83.9, "sqrt": 20.6, "fma64": 1.0, "imul": 1.08, "valu32": 0.71}
+# 4.30 for v_fma_f64).  "sin_phase" is the coupled kernels' sine of a
+# phase difference (reduction by pi, a degree-21 odd polynomial): 15
+# binary64 multiplies and FMAs, a rounding and a conversion (4.20 cycles
+# each) and two full-rate 32-bit operations (2.44), 18.1 slots.
+FP64_SLOTS = {"sin_phase": 18.1, "sin": 60.2, "log": 83.9, "sqrt": 20.6, "fma64": 1.0, "imul": 1.08,
+              "valu32": 0.71}
 
 
 def fp64_slots_per_orbit_step(n: int) -> dict:
@@ -71,8 +75,10 @@ def fp64_slots_per_orbit_step(n: int) -> dict:
     blocks = (n + 3) // 4
     bm = (n + 1) // 2
     counts = {
-        # per pair: the sine, one difference and two accumulations
-        "sin": pairs + 2 * bm,            # plus cos and sin of each Box-Muller pair
+        # per pair: the sine of the phase difference, one difference and two
+        # accumulations
+        "sin_phase": pairs,
+        "sin": 2 * bm,                    # cos and sin of each Box-Muller pair
         "log": bm, "sqrt": bm,
         # per pair 3 ops; per oscillator: two FMAs for the increment, the
         # state add and the 2 pi wrap (scale, round, two FMAs); per

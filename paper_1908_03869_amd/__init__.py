@@ -37,7 +37,7 @@ class Integrator:
         self.options = {"precision": 32, "method": 0, "observable": 0, "kernel": 0,
                         "shared_params": 0, "compensated": 1, "waves_per_cu": 0,
                         "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1, "drift": 0,
-                        "ode_limit": 0, "wrap": 1}
+                        "ode_limit": 0, "wrap": 1, "noise_waves": -1}
         for k, v in options.items():
             self.set_option(k, v)
 
@@ -54,7 +54,7 @@ class Integrator:
         self.options = {"precision": 32, "method": 0, "observable": 0, "kernel": 0,
                         "shared_params": 0, "compensated": 1, "waves_per_cu": 0,
                         "units_per_lane": 0, "graph": 1, "persistent": 1, "gemm": 1, "drift": 0,
-                        "ode_limit": 0, "wrap": 1}
+                        "ode_limit": 0, "wrap": 1, "noise_waves": -1}
         for k, v in options.items():
             self.set_option(k, v)
         return self

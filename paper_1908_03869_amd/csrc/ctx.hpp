@@ -31,6 +31,9 @@ struct sode_ctx {
     // Kuramoto phases: 1 = every kernel returns them reduced to [-pi, pi];
     // 0 = continuous phases (one-orbit-per-lane kernel only).
     int wrap = 1;
+    // Binary64 four-lane Kuramoto form: waves drawing the normals per
+    // integrating wave (0, 1 or 2); -1 = by ensemble size.
+    int noise_waves = -1;
     // Ragged batches: 0 = autotuned.
     int waves_per_cu = 0;
     int units_per_lane = 0;

@@ -5,8 +5,9 @@
 // paper measured in (Sec. 2.2.1): lane l of a 16-lane DPP row owns the
 // P = ceil(N/16) oscillators P*l .. P*l+P-1 (rows of N < 16P padded with
 // oscillators frozen at phase 0 whose terms are cancelled, as in the binary32
-// kernel); every unordered pair {i, j} is evaluated once with the device
-// library's binary64 sine and used for both oscillators; 64-bit values cross
+// kernel); every unordered pair {i, j} is evaluated once, with a binary64
+// sine for the bounded arguments these phases give (sin_phase64), and used
+// for both oscillators; 64-bit values cross
 // lanes as two 32-bit DPP row rotations.  The state is kept in radians and
 // wrapped to [-pi, pi] every step (theta - k 2pi_hi - k 2pi_lo, no rounding
 // when k = 0).  Normals are the binary64 Box-Muller pairs of the plain
@@ -54,6 +55,40 @@ __device__ __forceinline__ double wrap64(double x)
 
 __device__ __forceinline__ double load_phase64(double x) { return fabs(x) <= kPi ? x : wrap64(x); }
 
+// sin(x) for the kernels' arguments, differences of wrapped phases and the
+// phases themselves (|x| <= 2 pi plus a few ulp; accurate for |x| up to
+// about 2^20).  x = k pi + r with k = rint(x / pi), |r| <= pi/2, pi taken as
+// two binary64 parts (Cody and Waite's reduction: the first product is exact
+// for these k, so r is within an ulp); sin(x) = (-1)^k sin(r), the sign put
+// on r since sin is odd; sin(r) = r + r^3 q(r^2) with q the Maclaurin series
+// of (sin r - r) / r^3 through the r^21 term (Horner's scheme), whose
+// truncation error is below the next term, (pi/2)^23 / 23! = 1.3e-18.  About
+// 1.5 ulp in all; sixteen binary64 operations and three integer ones where
+// the device library spends about sixty binary64 issue slots on its general
+// reduction.  NaN and infinities give NaN.
+constexpr double kInvPi = 0.31830988618379067154;
+constexpr double kPiLo = 1.2246467991473531772e-16;   // pi - kPi
+__device__ __forceinline__ double sin_phase64(double x)
+{
+    const double k = rint(x * kInvPi);
+    double r = fma(-k, kPi, x);
+    r = fma(-k, kPiLo, r);
+    const uint64_t odd = (uint64_t)((int)k & 1) << 63;
+    r = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, r) ^ odd);
+    const double r2 = r * r;
+    double q = 1.9572941063391261231e-20;        //  1 / 21!
+    q = fma(q, r2, -8.2206352466243297170e-18);  // -1 / 19!
+    q = fma(q, r2, 2.8114572543455207632e-15);   //  1 / 17!
+    q = fma(q, r2, -7.6471637318198164759e-13);  // -1 / 15!
+    q = fma(q, r2, 1.6059043836821614599e-10);   //  1 / 13!
+    q = fma(q, r2, -2.5052108385441718775e-08);  // -1 / 11!
+    q = fma(q, r2, 2.7557319223985890653e-06);   //  1 / 9!
+    q = fma(q, r2, -1.9841269841269841270e-04);  // -1 / 7!
+    q = fma(q, r2, 8.3333333333333333333e-03);   //  1 / 5!
+    q = fma(q, r2, -1.6666666666666666667e-01);  // -1 / 3!
+    return fma(r * r2, q, r);
+}
+
 // Pairs between this lane and the lane K rotations away (K = 1..7): this
 // lane evaluates them and returns the negated partial sums with the inverse
 // rotation.
@@ -68,7 +103,7 @@ __device__ __forceinline__ void couple_across64(const double (&th)[P], double (&
     for (int a = 0; a < P; ++a) {
 #pragma unroll
         for (int b = 0; b < P; ++b) {
-            const double s = sin(other[b] - th[a]);
+            const double s = sin_phase64(other[b] - th[a]);
             acc[a] += s;
             back[b] = a == 0 ? s : back[b] + s;
         }
@@ -91,7 +126,7 @@ __device__ __forceinline__ void coupling_sums64(const double (&th)[P], double (&
         for (int a = 0; a < P; ++a) {
 #pragma unroll
             for (int b = a + 1; b < P; ++b) {
-                const double s = sin(th[b] - th[a]);
+                const double s = sin_phase64(th[b] - th[a]);
                 acc[a] = (a == 0 && b == 1) ? s : acc[a] + s;
                 acc[b] = a == 0 ? -s : acc[b] - s;
             }
@@ -106,7 +141,7 @@ __device__ __forceinline__ void coupling_sums64(const double (&th)[P], double (&
     for (int a = 0; a < P; ++a) {
 #pragma unroll
         for (int b = 0; b < P; ++b)
-            acc[a] += sin(other[b] - th[a]);
+            acc[a] += sin_phase64(other[b] - th[a]);
     }
 }
 
@@ -285,7 +320,7 @@ __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64
             if constexpr (PAD) {
 #pragma unroll
                 for (int i = 0; i < P; ++i)
-                    acc[i] = fma(pads, sin(th[i]), acc[i]);
+                    acc[i] = fma(pads, sin_phase64(th[i]), acc[i]);
             }
         }
 #pragma unroll
@@ -400,11 +435,11 @@ __global__ __launch_bounds__(256) void kuramoto_quad64_kernel(const Coupled64Arg
             const double C = quad_sum64(cs * w), S = quad_sum64(sn * w);
             acc = cs * S - sn * C;
         } else {
-            const double s1 = sin(quad_perm64<kQuadNext>(th) - th);
+            const double s1 = sin_phase64(quad_perm64<kQuadNext>(th) - th);
             acc = s1 - quad_perm64<kQuadPrev>(s1);
-            acc += sin(quad_perm64<kQuadOpp>(th) - th);
+            acc += sin_phase64(quad_perm64<kQuadOpp>(th) - th);
             if constexpr (PAD)
-                acc = fma(pads, sin(th), acc);
+                acc = fma(pads, sin_phase64(th), acc);
         }
         th = wrap64(th + (fma(kc, acc, drift0) + noise * xi));
     };
@@ -431,9 +466,205 @@ __global__ __launch_bounds__(256) void kuramoto_quad64_kernel(const Coupled64Arg
     }
 }
 
+// The four-lane form with its normals drawn by other waves.  An ensemble
+// too small to fill the chip leaves one wave alone on its SIMD, so a step
+// costs the latency of its dependent chain, and at n <= 4 the binary64
+// Box-Muller pairs (a logarithm, a square root, a sine and a cosine per two
+// normals) are most of that chain.  The normals do not depend on the state,
+// so a workgroup is one integrating wave (16 orbits, a quad each) and NW
+// waves that draw the normals of those orbits a batch of kQuadBatch steps
+// ahead into LDS, double-buffered, with one workgroup barrier per batch.
+// Each normal comes from the same Philox block (step, orbit id, 0) as in the
+// unstaged form, so the two give bitwise the same result.
+constexpr int kQuadBatch = 32;
+constexpr int kQuadOrbitsPerGroup = 16;
+struct QuadStage {
+    double xi[2][kQuadBatch][64];  // [buffer][step of the batch][integrating lane]
+};
+
+// Steps of the call (a multiple of the save stride) and batches of them.
+__device__ __forceinline__ int64_t quad_steps(const Coupled64Args& a) { return (a.nsave - 1) * a.stride; }
+
+template <bool PAD, bool MF>
+__device__ __forceinline__ void quad64_integrate(const Coupled64Args& a, int lane, int64_t o0, QuadStage& sh,
+                                                 int64_t nbatch)
+{
+    const int l = lane & 3;
+    const int64_t o = o0 + (lane >> 2);
+    // A quad past the last orbit runs on zeros (whole quads, so no quad_perm
+    // mixes it with a live orbit) and saves nothing.
+    const bool live = o < a.orbits;
+    const int n = PAD ? a.n : 4;
+    const double* __restrict__ p = a.p + (a.p_per_orbit && live ? o * (int64_t)(2 * n + 1) : 0);
+    const int q = a.observable == kKuramotoR ? 1 : n;
+    double* __restrict__ out_row = a.out + (live ? o : 0) * a.nsave * q;
+
+    const bool real = live && (!PAD || l < n);
+    double th = real ? load_phase64(a.X0[o * n + l]) : 0.0;
+    const double drift0 = real ? p[1 + l] * a.dt : 0.0;
+    const double noise = real ? p[1 + n + l] * a.sqdt : 0.0;
+    const double kc = real ? p[0] * (a.dt / (double)n) : 0.0;
+    const double w = real ? 1.0 : 0.0;
+    const double pads = (double)(4 - n);
+
+    auto save = [&](int64_t s) {
+        if (a.observable == kKuramotoR) {
+            const double C = quad_sum64(cos(th) * w), S = quad_sum64(sin(th) * w);
+            const double r = sqrt(C * C + S * S) / (double)n;
+            if (live && l == 0) {
+                note_nonfinite(a.nonfinite, r);
+                out_row[s] = r;
+            }
+        } else if (real) {
+            note_nonfinite(a.nonfinite, th);
+            out_row[s * n + l] = th;
+        }
+    };
+    auto step = [&](double xi) {
+        double acc;
+        if constexpr (MF) {
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            const double C = quad_sum64(cs * w), S = quad_sum64(sn * w);
+            acc = cs * S - sn * C;
+        } else {
+            const double s1 = sin_phase64(quad_perm64<kQuadNext>(th) - th);
+            acc = s1 - quad_perm64<kQuadPrev>(s1);
+            acc += sin_phase64(quad_perm64<kQuadOpp>(th) - th);
+            if constexpr (PAD)
+                acc = fma(pads, sin_phase64(th), acc);
+        }
+        th = wrap64(th + (fma(kc, acc, drift0) + noise * xi));
+    };
+
+    save(0);
+    const int64_t nsteps = quad_steps(a);
+    // Steps left until the next save and the next save's index: the same in
+    // every lane (scalar).
+    int64_t s = 1, to_save = a.stride;
+    for (int64_t bi = 0; bi < nbatch; ++bi) {
+        __syncthreads();  // the noise waves have staged batch bi
+        const double* __restrict__ src = &sh.xi[bi & 1][0][lane];
+        const int64_t k0 = bi * kQuadBatch;
+        if (k0 + kQuadBatch <= nsteps) {
+            double xi = src[0];
+#pragma unroll 4
+            for (int t = 0; t < kQuadBatch; ++t) {
+                const double xn = src[(t + 1 < kQuadBatch ? t + 1 : t) * 64];  // read ahead
+                step(xi);
+                if (--to_save == 0) {
+                    save(s);
+                    ++s;
+                    to_save = a.stride;
+                }
+                xi = xn;
+            }
+        } else {
+            for (int t = 0; k0 + t < nsteps; ++t) {
+                step(src[t * 64]);
+                if (--to_save == 0) {
+                    save(s);
+                    ++s;
+                    to_save = a.stride;
+                }
+            }
+        }
+    }
+}
+
+// Noise wave w (0 .. NW-1): lane = orbit (lane & 15) of the group and step
+// phase (lane >> 4) + 4 w, so the NW waves draw every step of a batch once:
+// one Philox block and its two Box-Muller pairs per orbit and step, the four
+// normals written to the four lanes of the orbit's quad.
+template <int NW>
+__device__ __forceinline__ void quad64_draw(const Coupled64Args& a, int w, int lane, int64_t o0, QuadStage& sh,
+                                            int64_t nbatch)
+{
+    static_assert(kQuadBatch % (4 * NW) == 0, "steps of a batch per noise lane");
+    const int q = lane & 15;
+    const int t0 = (lane >> 4) + 4 * w;
+    // Past the last orbit: the stream of the last one, drawn for lanes that
+    // never save.
+    const int64_t o = o0 + q < a.orbits ? o0 + q : a.orbits - 1;
+    const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
+    auto draw = [&](int64_t bi) {
+        double* __restrict__ dst = &sh.xi[bi & 1][0][4 * q];
+        const uint32_t k0 = (uint32_t)a.step_offset + (uint32_t)(bi * kQuadBatch);
+#pragma unroll 2
+        for (int i = 0; i < kQuadBatch / (4 * NW); ++i) {
+            const int t = t0 + 4 * NW * i;
+            const Block4 wd = philox_4x32_10(k0 + (uint32_t)t, st.oid, 0u, 0u, st.key_lo, st.key_hi);
+            double z0, z1, z2, z3;
+            box_muller_f64(wd.w0, wd.w1, z0, z1);
+            box_muller_f64(wd.w2, wd.w3, z2, z3);
+            double* __restrict__ at = dst + t * 64;
+            at[0] = z0;
+            at[1] = z1;
+            at[2] = z2;
+            at[3] = z3;
+        }
+    };
+    if (nbatch > 0)
+        draw(0);
+    for (int64_t bi = 0; bi < nbatch; ++bi) {
+        __syncthreads();  // matches the integrating wave's barrier before batch bi
+        if (bi + 1 < nbatch)
+            draw(bi + 1);  // the buffer batch bi - 1 used, read before this barrier
+    }
+}
+
+template <bool PAD, bool MF, int NW>
+__global__ __launch_bounds__(64 * (1 + NW)) void kuramoto_quad64_staged_kernel(const Coupled64Args a)
+{
+    __shared__ QuadStage sh;
+    // Uniform in each wave, so the integrate / draw branch is scalar and
+    // every wave reaches the same number of barriers (one per batch).
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int64_t o0 = (int64_t)blockIdx.x * kQuadOrbitsPerGroup;
+    const int64_t nbatch = (quad_steps(a) + kQuadBatch - 1) / kQuadBatch;
+    if (wave == 0)
+        quad64_integrate<PAD, MF>(a, lane, o0, sh, nbatch);
+    else
+        quad64_draw<NW>(a, wave - 1, lane, o0, sh, nbatch);
+}
+
+template <bool PAD, bool MF>
+hipError_t launch_quad64_staged(const Request& r, const Coupled64Args& a, int nw)
+{
+    const dim3 grid((unsigned)((r.orbits + kQuadOrbitsPerGroup - 1) / kQuadOrbitsPerGroup));
+    if (nw == 2)
+        hipLaunchKernelGGL((kuramoto_quad64_staged_kernel<PAD, MF, 2>), grid, dim3(192), 0, r.stream, a);
+    else
+        hipLaunchKernelGGL((kuramoto_quad64_staged_kernel<PAD, MF, 1>), grid, dim3(128), 0, r.stream, a);
+    return hipGetLastError();
+}
+
+// Noise waves per integrating wave of the four-lane form: the request's
+// choice, or by ensemble size.  Up to two workgroups per compute unit, two
+// (the noise then keeps up with an integrating wave that has a SIMD to
+// itself); up to one integrating wave per SIMD (four per compute unit),
+// one; beyond that none: the SIMDs are shared and the waves of other
+// orbits fill each other's gaps, so moving the normals to other waves only
+// adds their LDS traffic and barriers.
+int quad64_noise_waves(const Request& r)
+{
+    if (r.noise_waves >= 0)
+        return r.noise_waves;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    const int64_t groups = (r.orbits + kQuadOrbitsPerGroup - 1) / kQuadOrbitsPerGroup;
+    return groups <= 2 * (int64_t)cus ? 2 : groups <= 4 * (int64_t)cus ? 1 : 0;
+}
+
 template <bool PAD>
 hipError_t launch_quad64(const Request& r, const Coupled64Args& a)
 {
+    const int nw = quad64_noise_waves(r);
+    if (nw > 0)
+        return r.drift == 1 ? launch_quad64_staged<PAD, true>(r, a, nw) : launch_quad64_staged<PAD, false>(r, a, nw);
     const int64_t threads = r.orbits * 4;
     const dim3 block(256);
     const dim3 grid((unsigned)((threads + 255) / 256));

@@ -29,6 +29,7 @@ struct Request {
     int compensated;  // binary32 coupled kernels: state carried as hi + lo (Fast2Sum)
     int drift;        // Kuramoto coupling sum: 0 pairwise, 1 mean-field identity
     int wrap;         // Kuramoto: phases reduced to [-pi, pi] (the coupled kernels always do)
+    int noise_waves;  // binary64 four-lane Kuramoto: waves drawing normals per integrating wave, -1 auto
     void* out;  // [orbits][nsave][q]
     int* nonfinite;  // device flag raised by a NaN or infinite save (may be null)
     hipStream_t stream;

@@ -334,6 +334,10 @@ int sode_set_option(sode_t h, const char* key, int64_t value)
         if (value != 0 && value != 1)
             return SODE_EINVAL;
         h->wrap = (int)value;
+    } else if (std::strcmp(key, "noise_waves") == 0) {
+        if (value < -1 || value > 2)
+            return SODE_EINVAL;
+        h->noise_waves = (int)value;
     } else {
         return SODE_EINVAL;
     }
@@ -372,6 +376,8 @@ int sode_get_option(sode_t h, const char* key, int64_t* value)
         *value = h->ode_limit;
     else if (std::strcmp(key, "wrap") == 0)
         *value = h->wrap;
+    else if (std::strcmp(key, "noise_waves") == 0)
+        *value = h->noise_waves;
     else if (std::strcmp(key, "ragged_waves_per_cu") == 0)
         *value = h->rg_last_waves;
     else if (std::strcmp(key, "ragged_units_per_lane") == 0)
@@ -434,6 +440,7 @@ int sode_integrate_ex(sode_t h, const void* X0, const void* p, int64_t orbits, d
     r.compensated = h->compensated;
     r.drift = h->drift;
     r.wrap = h->model == sode::kKuramoto && h->wrap ? 1 : 0;
+    r.noise_waves = h->noise_waves;
     r.out = out;
     r.stream = static_cast<hipStream_t>(stream);
     r.nonfinite = sode::nonfinite_flag(h);

@@ -29,7 +29,7 @@ def run_library(w: dict, *, precision: int, kernel: str = "auto", method: str = 
                 orbit_offset: int = 0, step_offset: int = 0, t0: float | None = None,
                 orbit_ids=None, orbit_seeds=None, shared: bool | None = None,
                 compensated: int = 1, drift: int = 0, wrap: int = 1, ode_limit: int | None = None,
-                device="cuda:0") -> np.ndarray:
+                noise_waves: int = -1, device="cuda:0") -> np.ndarray:
     import torch
 
     dtype = torch.float32 if precision == 32 else torch.float64
@@ -43,7 +43,7 @@ def run_library(w: dict, *, precision: int, kernel: str = "auto", method: str = 
     it = sode.Integrator(w["model"], w["n"], w["m"], w["d"], precision=precision,
                          method=OPT[method], observable=OPT[obs], kernel=OPT[kernel],
                          shared_params=int(shared), compensated=compensated, drift=drift,
-                         wrap=wrap, ode_limit=ode_limit)
+                         wrap=wrap, ode_limit=ode_limit, noise_waves=noise_waves)
     X0_t = torch.tensor(np.ascontiguousarray(X0), dtype=dtype, device=device)
     p_t = torch.tensor(np.ascontiguousarray(p), dtype=dtype, device=device)
     ids = orbit_ids if orbit_ids is not None else w.get("orbit_ids")

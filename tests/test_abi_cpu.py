@@ -282,6 +282,26 @@ def test_wrap_option_fixes_the_phase_convention():
         abi.sode_destroy(h)
 
 
+def test_noise_waves_option():
+    """"noise_waves": -1 (by ensemble size, the default), 0, 1 or 2 waves
+    drawing the normals of the binary64 four-lane form; anything else is
+    refused and leaves the handle unchanged."""
+    st, h = abi.sode_create("kuramoto", 4, 4, 9)
+    try:
+        assert abi.sode_get_option(h, "noise_waves") == (0, -1)
+        for v in (0, 1, 2, -1):
+            assert abi.sode_set_option(h, "noise_waves", v) == 0
+            assert abi.sode_get_option(h, "noise_waves") == (0, v)
+        abi.sode_set_option(h, "noise_waves", 2)
+        for v in (-2, 3, 64):
+            assert abi.sode_set_option(h, "noise_waves", v) == abi.SODE_EINVAL
+        assert abi.sode_get_option(h, "noise_waves") == (0, 2)
+        abi.sode_set_option(h, "precision", 64)
+        assert _call(h, orbits=0) == abi.SODE_OK
+    finally:
+        abi.sode_destroy(h)
+
+
 def _ragged(h, descs, x0_len=1000, p_len=1000, out_len=10**7, dt=1e-3):
     arr = (abi.SodeInstance * len(descs))(*descs) if descs else None
     return abi.sode_integrate_ragged(h, arr, len(descs), FAKE, x0_len, FAKE, p_len, FAKE, out_len,

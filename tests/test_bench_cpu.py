@@ -46,7 +46,7 @@ def test_fp64_work_counts_each_pair_once():
     Philox block."""
     import bench
     c = bench.fp64_slots_per_orbit_step(4)
-    assert (c["sin"], c["log"], c["sqrt"], c["imul"], c["valu32"]) == (10, 2, 2, 20, 20)
+    assert (c["sin_phase"], c["sin"], c["log"], c["sqrt"], c["imul"], c["valu32"]) == (6, 4, 2, 2, 20, 20)
     assert c["fma64"] == 3 * 6 + 7 * 4 + 7 * 2
     assert abs(c["slots"] - sum(c[k] * bench.FP64_SLOTS[k] for k in bench.FP64_SLOTS)) < 1e-9
 
