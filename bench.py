@@ -11,7 +11,10 @@ Printed JSON line (rank 0): the driver's contract fields plus
   cpu_baseline  the FP64 oracle timed on a bounded sample on the host,
   cpu_all_cores the same oracle over the 256 grid-diagonal orbits, one OS
                 thread per host core (disjoint orbit shards),
-  plain_fp64    the one-orbit-per-lane FP64 kernel on the same ensemble,
+  plain_fp64, lanes16_fp64
+                the one-orbit-per-lane and the 16-lane FP64 kernels on the
+                same ensemble, each with its binary64 roofline fraction,
+  small_fp64    the n = 4 binary64 ensemble (1024 orbits x 10^4 steps),
   error         max |dr| against the oracle on the sampled orbits (and on
                 all 256 diagonal orbits from the all-core run, with how
                 many are within the bound and, for the worst, how far the
@@ -55,17 +58,18 @@ COUPLED_N64_HBM_BYTES = 50.97e6 + 53.01e6
 # chip issues 256 * 4 * 16 * 2.4e9 = 3.93e13 binary64 FMA lane-slots/s, the
 # published 78.6 TFLOP/s binary64 vector peak.
 FP64_FMA_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-# Issue cost in binary64 FMA slots of one call of each device-library
-# binary64 function, of a v_mad_u64_u32 and of a v_bitop3_b32: measured
-# wave64 issue cycles of each divided by those of one v_fma_f64 (the op-rate
-# microbenchmark, bench.py --op-rates, four waves per SIMD: sin/cos 258.7,
-# log 360.8, sqrt 88.6, v_mad_u64_u32 4.66, v_bitop3_b32 3.04 cycles against
-# 4.30 for v_fma_f64).  "sin_phase" is the coupled kernels' sine of a
-# phase difference (reduction by pi, a degree-21 odd polynomial): 15
-# binary64 multiplies and FMAs, a rounding and a conversion (4.20 cycles
-# each) and two full-rate 32-bit operations (2.44), 18.1 slots.
-FP64_SLOTS = {"sin_phase": 18.1, "sin": 60.2, "log": 83.9, "sqrt": 20.6, "fma64": 1.0, "imul": 1.08,
-              "valu32": 0.71}
+# Issue cost in binary64 FMA slots of each operation class of the binary64
+# Kuramoto step: measured wave64 issue cycles (the op-rate microbenchmark,
+# bench.py --op-rates, four waves per SIMD) divided by the 4.30 cycles of one
+# v_fma_f64.  "sin_phase" is the coupled kernels' sine of a phase difference
+# (81.3 cycles per call), "box_muller_pair" their pair of normals from two
+# 24-bit uniforms with the logarithm, square root, cosine and sine (462.8
+# cycles; the pair on the library's log, sqrt and sincospi takes 666.9), both
+# as timed in a dependent chain that adds one binary64 add per call (and, for
+# the pair, the derivation of its words); "imul" a v_mad_u64_u32 (4.66),
+# "valu32" a v_bitop3_b32 (3.04).  Pricing each function at the cheapest
+# implementation measured keeps the work, and so the fraction, conservative.
+FP64_SLOTS = {"sin_phase": 18.9, "box_muller_pair": 107.6, "fma64": 1.0, "imul": 1.08, "valu32": 0.71}
 
 
 def fp64_slots_per_orbit_step(n: int) -> dict:
@@ -78,12 +82,10 @@ def fp64_slots_per_orbit_step(n: int) -> dict:
         # per pair: the sine of the phase difference, one difference and two
         # accumulations
         "sin_phase": pairs,
-        "sin": 2 * bm,                    # cos and sin of each Box-Muller pair
-        "log": bm, "sqrt": bm,
+        "box_muller_pair": bm,
         # per pair 3 ops; per oscillator: two FMAs for the increment, the
-        # state add and the 2 pi wrap (scale, round, two FMAs); per
-        # Box-Muller pair: two conversions, two scalings, radius, two products
-        "fma64": pairs * 3 + n * 7 + bm * 7,
+        # state add and the 2 pi wrap (scale, round, two FMAs)
+        "fma64": pairs * 3 + n * 7,
         # per Philox block: ten rounds of two 32 x 32 -> 64 products
         # (v_mad_u64_u32) and two three-way XORs
         "imul": blocks * 20,
@@ -452,7 +454,10 @@ def grid_fp64_leg(sode, torch, w, X0, p, dev, bsteps: int, rows, ref_rows=None) 
     """Binary64 kernels on the n = 64 grid ensemble, `bsteps` steps (their
     per-step cost does not depend on the step count): one orbit per lane (the
     plain FP64 per-orbit baseline) and 16 lanes per orbit.  Error: max |dr| at
-    the last step over the sampled orbits `rows` against the oracle."""
+    the last step over the sampled orbits `rows` against the oracle.  Each
+    carries the binary64 roofline of the small_fp64 leg: the formulation's
+    work per orbit-step (2016 pair sines for n = 64) in binary64 FMA slots
+    against the chip's binary64 issue peak; 65,536 orbits fill the chip."""
     import oracle
     n, orbits, stride = w["n"], X0.shape[0], w["stride"]
     X64, p64 = X0.double(), p.double()
@@ -463,6 +468,7 @@ def grid_fp64_leg(sode, torch, w, X0, p, dev, bsteps: int, rows, ref_rows=None) 
             w["p"][rows].astype(np.float32).astype(np.float64), 0.0, w["dt"], bsteps, bsteps,
             w["seed"], threads=host_threads()[1], orbit_ids=rows, observable="kuramoto_r")[:, -1, 0]
     res = {}
+    work = fp64_slots_per_orbit_step(n)
     for kernel, name in (("plain", "plain_fp64"), ("coupled", "lanes16_fp64")):
         it = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=64, observable="kuramoto_r",
                              kernel=kernel)
@@ -480,6 +486,11 @@ def grid_fp64_leg(sode, torch, w, X0, p, dev, bsteps: int, rows, ref_rows=None) 
                      "kernel_ms": ms,
                      "error": {"max_abs_dr": float(np.abs(r - ref_rows).max()), "orbits": len(rows),
                                "tolerance": 1e-4}}
+        achieved = work["slots"] * orbits * bsteps / (ms * 1e-3)
+        res[name]["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
+                                 "peak": FP64_FMA_SLOTS_PER_S / 1e12,
+                                 "unit": "T binary64 FMA lane-slots/s", "frac": achieved / FP64_FMA_SLOTS_PER_S,
+                                 "slots_per_orbit_step": work["slots"]}
         it.close()
     return res
 
@@ -599,7 +610,7 @@ def op_rates(waves_per_simd=(1, 2, 4)) -> None:
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     for op in range(L.op_rates_count()):
         name = L.op_rates_name(op).decode()
-        library = "library call" in name
+        library = "library call" in name or "per call" in name
         iters = 100 if library else 4000
         for W in waves_per_simd:
             span, ms = ctypes.c_double(), ctypes.c_double()

@@ -10,13 +10,16 @@
 // for both oscillators; 64-bit values cross
 // lanes as two 32-bit DPP row rotations.  The state is kept in radians and
 // wrapped to [-pi, pi] every step (theta - k 2pi_hi - k 2pi_lo, no rounding
-// when k = 0).  Normals are the binary64 Box-Muller pairs of the plain
-// kernel and the oracle.  Compared with one orbit per lane it moves 16x
+// when k = 0).  Normals come from the same Philox blocks and uniforms as the
+// plain kernel's and the oracle's, through a Box-Muller pair that uses that
+// the uniforms are 24-bit (box_muller_f64_u24: within a few ulp of the
+// device library's functions, at well under half their issue cost).  Compared with one orbit per lane it moves 16x
 // more lanes through each step, which matters when the ensemble is too
 // small to fill the chip (Sec. 2.2.1 starts at 512 orbits).
 #include "devmath.hpp"
 #include "launch.hpp"
 #include "noise.hpp"
+#include "phase64.hpp"
 
 namespace sode {
 namespace {
@@ -54,40 +57,6 @@ __device__ __forceinline__ double wrap64(double x)
 }
 
 __device__ __forceinline__ double load_phase64(double x) { return fabs(x) <= kPi ? x : wrap64(x); }
-
-// sin(x) for the kernels' arguments, differences of wrapped phases and the
-// phases themselves (|x| <= 2 pi plus a few ulp; accurate for |x| up to
-// about 2^20).  x = k pi + r with k = rint(x / pi), |r| <= pi/2, pi taken as
-// two binary64 parts (Cody and Waite's reduction: the first product is exact
-// for these k, so r is within an ulp); sin(x) = (-1)^k sin(r), the sign put
-// on r since sin is odd; sin(r) = r + r^3 q(r^2) with q the Maclaurin series
-// of (sin r - r) / r^3 through the r^21 term (Horner's scheme), whose
-// truncation error is below the next term, (pi/2)^23 / 23! = 1.3e-18.  About
-// 1.5 ulp in all; sixteen binary64 operations and three integer ones where
-// the device library spends about sixty binary64 issue slots on its general
-// reduction.  NaN and infinities give NaN.
-constexpr double kInvPi = 0.31830988618379067154;
-constexpr double kPiLo = 1.2246467991473531772e-16;   // pi - kPi
-__device__ __forceinline__ double sin_phase64(double x)
-{
-    const double k = rint(x * kInvPi);
-    double r = fma(-k, kPi, x);
-    r = fma(-k, kPiLo, r);
-    const uint64_t odd = (uint64_t)((int)k & 1) << 63;
-    r = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, r) ^ odd);
-    const double r2 = r * r;
-    double q = 1.9572941063391261231e-20;        //  1 / 21!
-    q = fma(q, r2, -8.2206352466243297170e-18);  // -1 / 19!
-    q = fma(q, r2, 2.8114572543455207632e-15);   //  1 / 17!
-    q = fma(q, r2, -7.6471637318198164759e-13);  // -1 / 15!
-    q = fma(q, r2, 1.6059043836821614599e-10);   //  1 / 13!
-    q = fma(q, r2, -2.5052108385441718775e-08);  // -1 / 11!
-    q = fma(q, r2, 2.7557319223985890653e-06);   //  1 / 9!
-    q = fma(q, r2, -1.9841269841269841270e-04);  // -1 / 7!
-    q = fma(q, r2, 8.3333333333333333333e-03);   //  1 / 5!
-    q = fma(q, r2, -1.6666666666666666667e-01);  // -1 / 3!
-    return fma(r * r2, q, r);
-}
 
 // Pairs between this lane and the lane K rotations away (K = 1..7): this
 // lane evaluates them and returns the negated partial sums with the inverse
@@ -155,8 +124,8 @@ __device__ __forceinline__ void lane_normals64(const Stream& st, uint32_t k, int
 #pragma unroll
         for (int g = 0; g < P / 4; ++g) {
             const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)((P / 4) * l + g), 0u, st.key_lo, st.key_hi);
-            box_muller_f64(w.w0, w.w1, xi[4 * g + 0], xi[4 * g + 1]);
-            box_muller_f64(w.w2, w.w3, xi[4 * g + 2], xi[4 * g + 3]);
+            box_muller_f64_u24(w.w0, w.w1, xi[4 * g + 0], xi[4 * g + 1]);
+            box_muller_f64_u24(w.w2, w.w3, xi[4 * g + 2], xi[4 * g + 3]);
         }
     } else {
         constexpr int NB = (P + 6) / 4;  // ceil((P + 3) / 4) blocks at most
@@ -166,8 +135,8 @@ __device__ __forceinline__ void lane_normals64(const Stream& st, uint32_t k, int
 #pragma unroll
         for (int g = 0; g < NB; ++g) {
             const Block4 w = philox_4x32_10(k, st.oid, (uint32_t)((j0 >> 2) + g), 0u, st.key_lo, st.key_hi);
-            box_muller_f64(w.w0, w.w1, z[4 * g + 0], z[4 * g + 1]);
-            box_muller_f64(w.w2, w.w3, z[4 * g + 2], z[4 * g + 3]);
+            box_muller_f64_u24(w.w0, w.w1, z[4 * g + 0], z[4 * g + 1]);
+            box_muller_f64_u24(w.w2, w.w3, z[4 * g + 2], z[4 * g + 3]);
         }
 #pragma unroll
         for (int i = 0; i < P; ++i)
@@ -202,14 +171,14 @@ __device__ __forceinline__ void lane_normals64_steps(const Stream& st, uint32_t 
         const uint32_t own0 = odd ? w.w2 : w.w0, own1 = odd ? w.w3 : w.w1;
         const uint32_t got0 = from_pair_lane(odd ? w.w0 : w.w2);
         const uint32_t got1 = from_pair_lane(odd ? w.w1 : w.w3);
-        box_muller_f64(odd ? got0 : own0, odd ? got1 : own1, xi[0][0], xi[0][1]);
-        box_muller_f64(odd ? own0 : got0, odd ? own1 : got1, xi[1][0], xi[1][1]);
+        box_muller_f64_u24(odd ? got0 : own0, odd ? got1 : own1, xi[0][0], xi[0][1]);
+        box_muller_f64_u24(odd ? own0 : got0, odd ? own1 : got1, xi[1][0], xi[1][1]);
     } else {
         const int qi = l & 3;
         const Block4 w = philox_4x32_10(k + (uint32_t)qi, st.oid, (uint32_t)(l >> 2), 0u, st.key_lo, st.key_hi);
         double z0, z1, z2, z3;
-        box_muller_f64(w.w0, w.w1, z0, z1);
-        box_muller_f64(w.w2, w.w3, z2, z3);
+        box_muller_f64_u24(w.w0, w.w1, z0, z1);
+        box_muller_f64_u24(w.w2, w.w3, z2, z3);
         auto mine = [qi](double c0, double c1, double c2, double c3) {
             return (qi & 2) ? ((qi & 1) ? c3 : c2) : ((qi & 1) ? c1 : c0);
         };
@@ -595,8 +564,8 @@ __device__ __forceinline__ void quad64_draw(const Coupled64Args& a, int w, int l
             const int t = t0 + 4 * NW * i;
             const Block4 wd = philox_4x32_10(k0 + (uint32_t)t, st.oid, 0u, 0u, st.key_lo, st.key_hi);
             double z0, z1, z2, z3;
-            box_muller_f64(wd.w0, wd.w1, z0, z1);
-            box_muller_f64(wd.w2, wd.w3, z2, z3);
+            box_muller_f64_u24(wd.w0, wd.w1, z0, z1);
+            box_muller_f64_u24(wd.w2, wd.w3, z2, z3);
             double* __restrict__ at = dst + t * 64;
             at[0] = z0;
             at[1] = z1;

@@ -20,7 +20,9 @@
 // instructions per wave).  W = 1 shows what one wave alone can issue, W = 4
 // what the SIMD can.  The binary64 library functions (sin, cos, log, sqrt
 // of the device math library) are timed the same way over dependent call
-// chains, per call.
+// chains, per call, and so are the coupled kernels' own binary64 sine of a
+// phase difference and their Box-Muller pair beside the library-function
+// one.
 //
 // Only ALU work, one store per lane (to a buffer of one float per lane) and
 // two per wave (its two clock readings).
@@ -28,6 +30,9 @@
 
 #include <cmath>
 #include <cstdint>
+
+#include "noise.hpp"
+#include "phase64.hpp"
 
 namespace {
 
@@ -61,6 +66,9 @@ enum Op : int {
     kLibLogF64,
     kLibSqrtF64,
     kLibSinF32,     // sinf of the device library (radians, with reduction)
+    kPhaseSinF64,   // the coupled kernels' binary64 sine of a phase difference
+    kBoxMullerLibF64,  // binary64 Box-Muller pair on the library's log, sqrt, sincospi
+    kBoxMullerU24F64,  // the same pair with the 24-bit-uniform log and cos / sin
     kOpCount
 };
 
@@ -73,7 +81,9 @@ const char* const kNames[kOpCount] = {
     "mix: 4 pairs, partner read folded (4 sub_dpp, 4 sin, 8 add)",
     "mix: 4 pairs, partner read once (mov_dpp, 4 sub, 4 sin, 8 add)", "binary64 sin (library call)",
     "binary64 cos (library call)", "binary64 log (library call)", "binary64 sqrt (library call)",
-    "binary32 sinf (library call)"};
+    "binary32 sinf (library call)", "binary64 sin_phase64 (coupled kernels' sine, per call)",
+    "binary64 Box-Muller pair, library log/sqrt/sincospi (per call)",
+    "binary64 Box-Muller pair, 24-bit-uniform log and cos/sin (per call)"};
 
 // Instructions (or library calls) per chain per block.
 // Instructions (or library calls) per block of 8 chains.
@@ -249,13 +259,34 @@ __device__ __forceinline__ void block_f64(double (&x)[kChains], double y)
 #define X(i) x[i] = sqrt(x[i]) + y;
         SODE_R8(X)
 #undef X
+    } else if constexpr (OP == kPhaseSinF64) {
+#define X(i) x[i] = sode::sin_phase64(x[i]) + y;
+        SODE_R8(X)
+#undef X
+    } else if constexpr (OP == kBoxMullerLibF64 || OP == kBoxMullerU24F64) {
+        // Words from the chain's bits (two integer multiplies and a shift),
+        // so every call sees new uniforms; the pair's sum feeds the chain.
+#define X(i)                                                                          \
+    {                                                                                 \
+        const uint64_t bx = __builtin_bit_cast(uint64_t, x[i]);                       \
+        const uint32_t wa = (uint32_t)bx * 2654435761u, wb = (uint32_t)(bx >> 20) * 40503u; \
+        double zc, zs;                                                                \
+        if constexpr (OP == kBoxMullerLibF64)                                         \
+            sode::box_muller_f64(wa, wb, zc, zs);                                     \
+        else                                                                          \
+            sode::box_muller_f64_u24(wa, wb, zc, zs);                                 \
+        x[i] = (zc + zs) + y;                                                         \
+    }
+        SODE_R8(X)
+#undef X
     }
 }
 
 constexpr bool is_u32(int op) { return op == kMulHiU32 || op == kMadU64U32 || op == kBitop3; }
 constexpr bool is_f64(int op)
 {
-    return op == kFmaF64 || op == kLibSinF64 || op == kLibCosF64 || op == kLibLogF64 || op == kLibSqrtF64;
+    return op == kFmaF64 || op == kLibSinF64 || op == kLibCosF64 || op == kLibLogF64 || op == kLibSqrtF64 ||
+           op == kPhaseSinF64 || op == kBoxMullerLibF64 || op == kBoxMullerU24F64;
 }
 
 // out: one float per lane of the grid; stamps: the shader-clock readings

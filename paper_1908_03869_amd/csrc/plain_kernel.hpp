@@ -208,8 +208,14 @@ __device__ __forceinline__ void plain_body(const PlainArgs<R>& a)
                 for (int j = m; j < n; ++j)
                     xi[j] = 0;
                 Model::diffuse(n, t, p, y, xi);
-                for (int i = 0; i < n; ++i)
-                    y[i] = y[i] + f[i] * a.dt + xi[i] * a.sqdt;
+                // The phase reduction (below for the other methods) in the
+                // same pass: with a run-time n the state lives in scratch
+                // memory, and a second pass over it costs a visible share
+                // of a step.
+                for (int i = 0; i < n; ++i) {
+                    const R v = y[i] + f[i] * a.dt + xi[i] * a.sqdt;
+                    y[i] = a.wrap ? dev_wrap_phase(v) : v;
+                }
             } else if constexpr (METH == kMilstein) {
                 R f[CAP], xi[XCAP], gxi[XCAP], c[CAP];
                 Model::drift(n, t, p, y, f);
@@ -252,7 +258,7 @@ __device__ __forceinline__ void plain_body(const PlainArgs<R>& a)
                 const R c = METH == kImplicitEuler ? (R)1 : (R)0.5;
                 implicit_step<Model, R, ICAP>(n, t, a.dt, c, p, y);
             }
-            if (a.wrap) {  // the drift is 2 pi periodic in every phase
+            if (METH != kEM && a.wrap) {  // the drift is 2 pi periodic in every phase
                 for (int i = 0; i < n; ++i)
                     y[i] = dev_wrap_phase(y[i]);
             }

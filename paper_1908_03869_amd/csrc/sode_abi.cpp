@@ -149,8 +149,12 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
     } else if (coupled_ok && h->precision == 32 && (h->n >= 5 || orbits <= 65536)) {
         *kernel = 2;
     } else if (coupled_ok && h->precision == 64 &&
-               (h->n <= 4 || (h->n <= 16 && (h->n >= 10 || (h->drift == 1 ? orbits <= 65536
-                                                                         : orbits <= 400 * (int64_t)h->n * h->n))))) {
+               (h->n <= 4 || (h->n <= 16 && (h->n >= 10 || (h->drift == 1 ? orbits <= 18000 * (int64_t)h->n
+                                                                         : orbits <= 2400 * (int64_t)h->n * h->n))))) {
+        // Binary64, 5 <= n <= 9: a padded 16-lane row costs the same for any
+        // n <= 16 and one orbit per lane ~n^2 (pairwise) or ~n (mean-field)
+        // per orbit-step; the crossovers measured at n = 5 (between 40,960
+        // and 81,920 orbits pairwise, near 90,000 mean-field) scale with that.
         *kernel = 2;
     } else if (matrix_ok) {
         *kernel = 3;

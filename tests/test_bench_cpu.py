@@ -41,13 +41,14 @@ def test_headline_workload_slot_count():
 
 
 def test_fp64_work_counts_each_pair_once():
-    """The binary64 roofline's work for n = 4: six pair sines plus the sine and
-    cosine of two Box-Muller pairs, two logarithms and square roots, one
-    Philox block."""
+    """The binary64 roofline's work for n = 4: six pair sines, two Box-Muller
+    pairs, one Philox block; for n = 64: 2016 pair sines, 32 pairs, 16 blocks."""
     import bench
     c = bench.fp64_slots_per_orbit_step(4)
-    assert (c["sin_phase"], c["sin"], c["log"], c["sqrt"], c["imul"], c["valu32"]) == (6, 4, 2, 2, 20, 20)
-    assert c["fma64"] == 3 * 6 + 7 * 4 + 7 * 2
+    assert (c["sin_phase"], c["box_muller_pair"], c["imul"], c["valu32"]) == (6, 2, 20, 20)
+    assert c["fma64"] == 3 * 6 + 7 * 4
+    c64 = bench.fp64_slots_per_orbit_step(64)
+    assert (c64["sin_phase"], c64["box_muller_pair"], c64["imul"]) == (2016, 32, 320)
     assert abs(c["slots"] - sum(c[k] * bench.FP64_SLOTS[k] for k in bench.FP64_SLOTS)) < 1e-9
 
 
