@@ -393,9 +393,15 @@ __device__ __forceinline__ void run_any(const RaggedKernelArgs& a, int32_t g, in
         run_shape<false>(a, g, wave, lane, sh);
 }
 
-// Persistent: every workgroup pops group indices until the list is
-// exhausted (an exit both waves reach: they read the same ticket).  Thread
-// 0 takes the ticket with a vector atomic and publishes it through LDS.
+// Persistent: workgroup b first runs group b, then pops group indices
+// gridDim.x, gridDim.x + 1, ... until the list is exhausted (an exit both
+// waves reach: they read the same ticket).  Thread 0 takes the ticket with a
+// vector atomic and publishes it through LDS.  The static first pass hands
+// the heaviest groups (the list is in decreasing cost) to consecutive
+// workgroups, which the dispatcher spreads over the chip; popped from the
+// queue, they went to whichever workgroups reached the counter first, often
+// neighbours on one compute unit, and the batch took 10.6-12.3 ms instead
+// of 10.4-10.7 ms from one launch to the next.
 __global__ __launch_bounds__(128) void fhn_ragged_persistent(const RaggedKernelArgs a)
 {
     __shared__ RaggedShared sh;
@@ -403,12 +409,15 @@ __global__ __launch_bounds__(128) void fhn_ragged_persistent(const RaggedKernelA
     // integrate / noise branch is a scalar branch.
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    for (;;) {
-        if (threadIdx.x == 0)
-            sh.ticket = (int32_t)atomicAdd(a.counter, 1u);
-        __syncthreads();
-        const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane(sh.ticket);
-        __syncthreads();  // both waves hold the ticket before it is replaced
+    for (uint32_t pass = 0;; ++pass) {
+        uint32_t g = blockIdx.x;
+        if (pass > 0) {
+            if (threadIdx.x == 0)
+                sh.ticket = (int32_t)(gridDim.x + atomicAdd(a.counter, 1u));
+            __syncthreads();
+            g = (uint32_t)__builtin_amdgcn_readfirstlane(sh.ticket);
+            __syncthreads();  // both waves hold the ticket before it is replaced
+        }
         if (g >= (uint32_t)a.ngroups)
             break;
         // The lane index passes through an empty asm statement on every

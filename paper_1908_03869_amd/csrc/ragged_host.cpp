@@ -252,7 +252,7 @@ int autotune(sode_ctx* h, const sode_instance_t* inst, int32_t count, const void
 {
     const int cus = compute_units();
     const int unit_choices[] = {1, 2, 4};
-    const int wave_choices[] = {4, 8, 16};
+    const int wave_choices[] = {2, 4, 8, 16};
     hipEvent_t t0, t1;
     if (hipEventCreate(&t0) != hipSuccess)
         return SODE_EDEVICE;
