@@ -62,14 +62,14 @@ FP64_FMA_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 # Kuramoto step: measured wave64 issue cycles (the op-rate microbenchmark,
 # bench.py --op-rates, four waves per SIMD) divided by the 4.30 cycles of one
 # v_fma_f64.  "sin_phase" is the coupled kernels' sine of a phase difference
-# (81.3 cycles per call), "box_muller_pair" their pair of normals from two
+# (73.0 cycles per call), "box_muller_pair" their pair of normals from two
 # 24-bit uniforms with the logarithm, square root, cosine and sine (462.8
 # cycles; the pair on the library's log, sqrt and sincospi takes 666.9), both
 # as timed in a dependent chain that adds one binary64 add per call (and, for
 # the pair, the derivation of its words); "imul" a v_mad_u64_u32 (4.66),
 # "valu32" a v_bitop3_b32 (3.04).  Pricing each function at the cheapest
 # implementation measured keeps the work, and so the fraction, conservative.
-FP64_SLOTS = {"sin_phase": 18.9, "box_muller_pair": 107.6, "fma64": 1.0, "imul": 1.08, "valu32": 0.71}
+FP64_SLOTS = {"sin_phase": 17.0, "box_muller_pair": 107.6, "fma64": 1.0, "imul": 1.08, "valu32": 0.71}
 
 
 def fp64_slots_per_orbit_step(n: int) -> dict:

@@ -30,14 +30,16 @@ constexpr double kSqrtHalf = 0.70710678118654752440;
 // about 2^20).  x = k pi + r with k = rint(x / pi), |r| <= pi/2, pi taken as
 // two binary64 parts (Cody and Waite's reduction: the first product is exact
 // for these k, so r is within an ulp); sin(x) = (-1)^k sin(r), the sign put
-// on r since sin is odd; sin(r) = r + r^3 q(r^2) with q the Maclaurin series
-// of (sin r - r) / r^3 through the r^21 term (Horner's scheme), whose
-// truncation error is below the next term, (pi/2)^23 / 23! = 1.3e-18.
-// Within 2 ulp (largest near pi/2, from the last rounding of r + r^3 q).
-// Compiled: 15 binary64 multiplies and FMAs, a rounding, a conversion and
-// two 32-bit operations, where the device library's sin spends about sixty
-// binary64 issue slots on a reduction built for any argument.  NaN and
-// infinities give NaN.
+// on r since sin is odd; sin(r) = r + r^3 q(r^2) with q of degree 7, the
+// polynomial interpolating (sin r - r) / r^3 at the 8 Chebyshev nodes of
+// [0, (pi/2)^2] (phase64_coefficients.py computes it exactly from the
+// Maclaurin series): relative error below 4e-17 before rounding, with two
+// multiply-adds fewer than the Maclaurin series through r^21 that it
+// replaces.  Within 2 ulp (largest near pi/2, from the last rounding of
+// r + r^3 q).  Compiled: 13 binary64 multiplies and FMAs, a rounding, a
+// conversion and two 32-bit operations, where the device library's sin
+// spends about sixty binary64 issue slots on a reduction built for any
+// argument.  NaN and infinities give NaN.
 __host__ __device__ __forceinline__ double sin_phase64(double x)
 {
     const double k = rint(x * phase64::kInvPi);
@@ -46,16 +48,14 @@ __host__ __device__ __forceinline__ double sin_phase64(double x)
     const uint64_t odd = (uint64_t)((int)k & 1) << 63;
     r = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, r) ^ odd);
     const double r2 = r * r;
-    double q = 1.9572941063391261231e-20;        //  1 / 21!
-    q = fma(q, r2, -8.2206352466243297170e-18);  // -1 / 19!
-    q = fma(q, r2, 2.8114572543455207632e-15);   //  1 / 17!
-    q = fma(q, r2, -7.6471637318198164759e-13);  // -1 / 15!
-    q = fma(q, r2, 1.6059043836821614599e-10);   //  1 / 13!
-    q = fma(q, r2, -2.5052108385441718775e-08);  // -1 / 11!
-    q = fma(q, r2, 2.7557319223985890653e-06);   //  1 / 9!
-    q = fma(q, r2, -1.9841269841269841270e-04);  // -1 / 7!
-    q = fma(q, r2, 8.3333333333333333333e-03);   //  1 / 5!
-    q = fma(q, r2, -1.6666666666666666667e-01);  // -1 / 3!
+    double q = 2.7314447669863995e-15;
+    q = fma(q, r2, -7.643970296798572e-13);
+    q = fma(q, r2, 1.6058977312464087e-10);
+    q = fma(q, r2, -2.5052107616996182e-08);
+    q = fma(q, r2, 2.7557319219163234e-06);
+    q = fma(q, r2, -0.00019841269841254974);
+    q = fma(q, r2, 0.008333333333333316);
+    q = fma(q, r2, -0.16666666666666666);
     return fma(r * r2, q, r);
 }
 
