@@ -759,6 +759,10 @@ def parse():
     ap.add_argument("--rnn-only", choices=("bf16", "bf16x3", "fp32"), default=None,
                     help="time only the dense-network workload with this matrix variant "
                          "(one warm-up and one timed launch) and print its JSON")
+    ap.add_argument("--small-fp64-only", action="store_true",
+                    help="time only the n = 4 binary64 ensemble (1024 orbits x 10^4 steps) on "
+                         "the auto-chosen and the one-orbit-per-lane kernels and print its JSON "
+                         "(with --no-cpu: without the oracle run)")
     ap.add_argument("--ragged-alone", type=int, default=None, metavar="INSTANCE",
                     help="time one instance of the ragged FHN workload alone (a batch of one; "
                          "one warm-up and one timed launch) and print its JSON")
@@ -806,6 +810,9 @@ def main():
         return
     if args.rnn_only:
         print(json.dumps(rnn_leg(sode, torch, workloads, dev, gemms=(args.rnn_only,))))
+        return
+    if args.small_fp64_only:
+        print(json.dumps(small_fp64_leg(sode, torch, workloads, dev, cpu=not args.no_cpu)))
         return
     if args.ragged_alone is not None:
         w = workloads.fhn_ragged()
