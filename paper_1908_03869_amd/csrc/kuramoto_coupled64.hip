@@ -220,39 +220,68 @@ __device__ __forceinline__ double order_parameter64(const double (&th)[P], const
     return sqrt(C * C + S * S) / (double)n;
 }
 
-template <int P, bool PAD, bool MF>
-__global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64Args a)
+// A binary64 value held by another lane of the same quad, selected by the
+// DPP quad_perm control CTRL (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double quad_perm64(double v)
 {
-    const int l = threadIdx.x & 15;
-    const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    // Whole rows are in or out together, so no rotation reads a finished lane.
-    if (o >= a.orbits)
-        return;
-    const int n = PAD ? a.n : 16 * P;
-    const double* __restrict__ p = a.p + (a.p_per_orbit ? o * (int64_t)(2 * n + 1) : 0);
-    const int q = a.observable == kKuramotoR ? 1 : n;
-    double* __restrict__ out_row = a.out + o * a.nsave * q;
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// quad_perm selections (lane i of a quad takes lane sel[i]):
+constexpr int kQuadNext = 0x39;  // [1, 2, 3, 0]: lane (l + 1) mod 4
+constexpr int kQuadPrev = 0x93;  // [3, 0, 1, 2]: lane (l - 1) mod 4
+constexpr int kQuadOpp = 0x4E;   // [2, 3, 0, 1]: lane (l + 2) mod 4
 
-    // Per oscillator: omega dt, p sqrt(dt), K dt / N, weight (0 for pads).
+__device__ __forceinline__ double quad_sum64(double v)
+{
+    v += quad_perm64<kQuadOpp>(v);
+    return v + quad_perm64<kQuadNext>(v);
+}
+
+// One orbit on a 16-lane row (Sec. 2.2.1, Eq. 5/6): lane l's P oscillators,
+// their per-oscillator constants (omega dt, p sqrt(dt), K dt / N, weight 0
+// for pads), the save of the state or of r, and one Euler-Maruyama step
+// with given normals.  A row past the last orbit (live = false) runs on
+// zeros and saves nothing; it reads no input.
+template <int P, bool PAD, bool MF>
+struct RowOrbit64 {
+    static constexpr int kLanes = 16;  // lanes per orbit
+    static constexpr int kNormals = P; // normals per lane and step
     double th[P], drift0[P], noise[P], kc[P], w[P];
-    const double kcv = p[0] * (a.dt / (double)n);
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int osc = P * l + i;
-        const bool real = !PAD || osc < n;
-        th[i] = real ? load_phase64(a.X0[o * n + osc]) : 0.0;
-        drift0[i] = real ? p[1 + osc] * a.dt : 0.0;
-        noise[i] = real ? p[1 + n + osc] * a.sqdt : 0.0;
-        kc[i] = real ? kcv : 0.0;
-        w[i] = real ? 1.0 : 0.0;
-    }
-    const double pads = (double)(16 * P - n);
-    const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
+    double pads;
+    double* __restrict__ out_row;
+    int l, n;
+    bool live;
 
-    auto save = [&](int64_t s) {
+    __device__ __forceinline__ RowOrbit64(const Coupled64Args& a, int64_t o, int lane, bool is_live)
+        : l(lane), n(PAD ? a.n : 16 * P), live(is_live)
+    {
+        const int64_t oc = live ? o : 0;
+        const double* __restrict__ p = a.p + (a.p_per_orbit ? oc * (int64_t)(2 * n + 1) : 0);
+        const int q = a.observable == kKuramotoR ? 1 : n;
+        out_row = a.out + oc * a.nsave * q;
+        const double kcv = live ? p[0] * (a.dt / (double)n) : 0.0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int osc = P * l + i;
+            const bool real = live && (!PAD || osc < n);
+            th[i] = real ? load_phase64(a.X0[o * n + osc]) : 0.0;
+            drift0[i] = real ? p[1 + osc] * a.dt : 0.0;
+            noise[i] = real ? p[1 + n + osc] * a.sqdt : 0.0;
+            kc[i] = real ? kcv : 0.0;
+            w[i] = real ? 1.0 : 0.0;
+        }
+        pads = (double)(16 * P - n);
+    }
+
+    __device__ __forceinline__ void save(const Coupled64Args& a, int64_t s)
+    {
         if (a.observable == kKuramotoR) {
             const double r = order_parameter64<P>(th, w, n);
-            if (l == 0) {
+            if (live && l == 0) {
                 note_nonfinite(a.nonfinite, r);
                 out_row[s] = r;
             }
@@ -260,16 +289,16 @@ __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64
 #pragma unroll
             for (int i = 0; i < P; ++i) {
                 const int osc = P * l + i;
-                if (!PAD || osc < n) {
+                if (live && (!PAD || osc < n)) {
                     note_nonfinite(a.nonfinite, th[i]);
                     out_row[s * n + osc] = th[i];
                 }
             }
         }
-    };
+    }
 
-    // One Euler-Maruyama step with the normals xi of step k.
-    auto step = [&](const double (&xi)[P]) {
+    __device__ __forceinline__ void step(const double (&xi)[P])
+    {
         double acc[P];
         if constexpr (MF) {
             // sum_j sin(theta_j - theta_i) = cos(theta_i) S - sin(theta_i) C.
@@ -295,9 +324,87 @@ __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64
 #pragma unroll
         for (int i = 0; i < P; ++i)
             th[i] = wrap64(th[i] + (fma(kc[i], acc[i], drift0[i]) + noise[i] * xi[i]));
-    };
+    }
+};
 
-    save(0);
+// n <= 4: one orbit per quad of lanes, one oscillator per lane (lanes
+// l >= n hold pads at phase 0, cancelled as in the row form).  Every
+// unordered pair is evaluated once: the pairs (l, l + 1 mod 4) by lane l,
+// which returns the negated sine to lane l + 1, and the pairs (l, l + 2
+// mod 4) by both of their lanes.  Two binary64 sines per lane and step
+// instead of the 16-lane row's eight (and 16 lanes per orbit instead of 4).
+template <bool PAD, bool MF>
+struct QuadOrbit64 {
+    static constexpr int kLanes = 4;
+    static constexpr int kNormals = 1;
+    double th, drift0, noise, kc, w, pads;
+    double* __restrict__ out_row;
+    int l, n;
+    bool live, real;
+
+    __device__ __forceinline__ QuadOrbit64(const Coupled64Args& a, int64_t o, int lane, bool is_live)
+        : l(lane), n(PAD ? a.n : 4), live(is_live), real(is_live && (!PAD || lane < n))
+    {
+        const int64_t oc = live ? o : 0;
+        const double* __restrict__ p = a.p + (a.p_per_orbit ? oc * (int64_t)(2 * n + 1) : 0);
+        const int q = a.observable == kKuramotoR ? 1 : n;
+        out_row = a.out + oc * a.nsave * q;
+        th = real ? load_phase64(a.X0[o * n + l]) : 0.0;
+        drift0 = real ? p[1 + l] * a.dt : 0.0;
+        noise = real ? p[1 + n + l] * a.sqdt : 0.0;
+        kc = real ? p[0] * (a.dt / (double)n) : 0.0;
+        w = real ? 1.0 : 0.0;
+        pads = (double)(4 - n);
+    }
+
+    __device__ __forceinline__ void save(const Coupled64Args& a, int64_t s)
+    {
+        if (a.observable == kKuramotoR) {
+            const double C = quad_sum64(cos(th) * w), S = quad_sum64(sin(th) * w);
+            const double r = sqrt(C * C + S * S) / (double)n;
+            if (live && l == 0) {
+                note_nonfinite(a.nonfinite, r);
+                out_row[s] = r;
+            }
+        } else if (real) {
+            note_nonfinite(a.nonfinite, th);
+            out_row[s * n + l] = th;
+        }
+    }
+
+    __device__ __forceinline__ void step(const double (&xi)[1])
+    {
+        double acc;
+        if constexpr (MF) {
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            const double C = quad_sum64(cs * w), S = quad_sum64(sn * w);
+            acc = cs * S - sn * C;
+        } else {
+            const double s1 = sin_phase64(quad_perm64<kQuadNext>(th) - th);
+            acc = s1 - quad_perm64<kQuadPrev>(s1);
+            acc += sin_phase64(quad_perm64<kQuadOpp>(th) - th);
+            if constexpr (PAD)
+                acc = fma(pads, sin_phase64(th), acc);
+        }
+        th = wrap64(th + (fma(kc, acc, drift0) + noise * xi[0]));
+    }
+};
+
+// The row and quad forms with each lane drawing its own normals (several
+// steps at a time where lanes share a Philox block), one orbit per row or
+// quad, 256-thread blocks.  Whole rows and quads are in or out together, so
+// no lane permutation reads a finished lane.
+template <int P, bool PAD, bool MF>
+__global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64Args a)
+{
+    const int l = threadIdx.x & 15;
+    const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    if (o >= a.orbits)
+        return;
+    RowOrbit64<P, PAD, MF> f(a, o, l, true);
+    const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
+    f.save(a, 0);
     uint32_t k = (uint32_t)a.step_offset;
     if constexpr (P <= 2) {
         // Normals of B = 4/P steps at a time (lane_normals64_steps).
@@ -310,10 +417,10 @@ __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64
 #pragma unroll
             for (int t = 0; t < B; ++t) {
                 if (t == 0 || j + t < nsteps) {
-                    step(xb[t]);
+                    f.step(xb[t]);
                     ++k;
                     if (--to_save == 0) {
-                        save(s);
+                        f.save(a, s);
                         ++s;
                         to_save = a.stride;
                     }
@@ -325,95 +432,23 @@ __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64
             for (int64_t kk = 0; kk < a.stride; ++kk, ++k) {
                 double xi[P];
                 lane_normals64<P>(st, k, l, xi);
-                step(xi);
+                f.step(xi);
             }
-            save(s);
+            f.save(a, s);
         }
     }
 }
 
-// A binary64 value held by another lane of the same quad, selected by the
-// DPP quad_perm control CTRL (two 32-bit moves).
-template <int CTRL>
-__device__ __forceinline__ double quad_perm64(double v)
-{
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-// quad_perm selections (lane i of a quad takes lane sel[i]):
-constexpr int kQuadNext = 0x39;  // [1, 2, 3, 0]: lane (l + 1) mod 4
-constexpr int kQuadPrev = 0x93;  // [3, 0, 1, 2]: lane (l - 1) mod 4
-constexpr int kQuadOpp = 0x4E;   // [2, 3, 0, 1]: lane (l + 2) mod 4
-
-__device__ __forceinline__ double quad_sum64(double v)
-{
-    v += quad_perm64<kQuadOpp>(v);
-    return v + quad_perm64<kQuadNext>(v);
-}
-
-// n <= 4: one orbit per quad of lanes, one oscillator per lane (lanes
-// l >= n hold pads at phase 0, cancelled as in the 16-lane kernel).  Every
-// unordered pair is evaluated once: the pairs (l, l + 1 mod 4) by lane l,
-// which returns the negated sine to lane l + 1, and the pairs (l, l + 2
-// mod 4) by both of their lanes.  Two binary64 sines per lane and step
-// instead of the 16-lane row's eight (and 16 lanes per orbit instead of 4).
-// The normals are lane_normals64_steps<1>: the quad is the orbit.
 template <bool PAD, bool MF>
 __global__ __launch_bounds__(256) void kuramoto_quad64_kernel(const Coupled64Args a)
 {
     const int l = threadIdx.x & 3;
     const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-    // Whole quads are in or out together, so no quad_perm reads a finished lane.
     if (o >= a.orbits)
         return;
-    const int n = PAD ? a.n : 4;
-    const double* __restrict__ p = a.p + (a.p_per_orbit ? o * (int64_t)(2 * n + 1) : 0);
-    const int q = a.observable == kKuramotoR ? 1 : n;
-    double* __restrict__ out_row = a.out + o * a.nsave * q;
-
-    const bool real = !PAD || l < n;
-    double th = real ? load_phase64(a.X0[o * n + l]) : 0.0;
-    const double drift0 = real ? p[1 + l] * a.dt : 0.0;
-    const double noise = real ? p[1 + n + l] * a.sqdt : 0.0;
-    const double kc = real ? p[0] * (a.dt / (double)n) : 0.0;
-    const double w = real ? 1.0 : 0.0;
-    const double pads = (double)(4 - n);
+    QuadOrbit64<PAD, MF> f(a, o, l, true);
     const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
-
-    auto save = [&](int64_t s) {
-        if (a.observable == kKuramotoR) {
-            const double C = quad_sum64(cos(th) * w), S = quad_sum64(sin(th) * w);
-            const double r = sqrt(C * C + S * S) / (double)n;
-            if (l == 0) {
-                note_nonfinite(a.nonfinite, r);
-                out_row[s] = r;
-            }
-        } else if (real) {
-            note_nonfinite(a.nonfinite, th);
-            out_row[s * n + l] = th;
-        }
-    };
-
-    auto step = [&](double xi) {
-        double acc;
-        if constexpr (MF) {
-            double sn, cs;
-            sincos(th, &sn, &cs);
-            const double C = quad_sum64(cs * w), S = quad_sum64(sn * w);
-            acc = cs * S - sn * C;
-        } else {
-            const double s1 = sin_phase64(quad_perm64<kQuadNext>(th) - th);
-            acc = s1 - quad_perm64<kQuadPrev>(s1);
-            acc += sin_phase64(quad_perm64<kQuadOpp>(th) - th);
-            if constexpr (PAD)
-                acc = fma(pads, sin_phase64(th), acc);
-        }
-        th = wrap64(th + (fma(kc, acc, drift0) + noise * xi));
-    };
-
-    save(0);
+    f.save(a, 0);
     uint32_t k = (uint32_t)a.step_offset;
     const int64_t nsteps = (a.nsave - 1) * a.stride;
     int64_t s = 1, to_save = a.stride;
@@ -423,10 +458,10 @@ __global__ __launch_bounds__(256) void kuramoto_quad64_kernel(const Coupled64Arg
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             if (t == 0 || j + t < nsteps) {
-                step(xb[t][0]);
+                f.step(xb[t]);
                 ++k;
                 if (--to_save == 0) {
-                    save(s);
+                    f.save(a, s);
                     ++s;
                     to_save = a.stride;
                 }
@@ -435,138 +470,52 @@ __global__ __launch_bounds__(256) void kuramoto_quad64_kernel(const Coupled64Arg
     }
 }
 
-// The four-lane form with its normals drawn by other waves.  An ensemble
-// too small to fill the chip leaves one wave alone on its SIMD, so a step
-// costs the latency of its dependent chain, and at n <= 4 the binary64
-// Box-Muller pairs (a logarithm, a square root, a sine and a cosine per two
-// normals) are most of that chain.  The normals do not depend on the state,
-// so a workgroup is one integrating wave (16 orbits, a quad each) and NW
-// waves that draw the normals of those orbits a batch of kQuadBatch steps
-// ahead into LDS, double-buffered, with one workgroup barrier per batch.
-// Each normal comes from the same Philox block (step, orbit id, 0) as in the
-// unstaged form, so the two give bitwise the same result.
-constexpr int kQuadBatch = 32;
-constexpr int kQuadOrbitsPerGroup = 16;
-struct QuadStage {
-    double xi[2][kQuadBatch][64];  // [buffer][step of the batch][integrating lane]
+// The same forms with their normals drawn by other waves.  An ensemble too
+// small to fill the chip leaves one wave alone on its SIMD, so a step costs
+// the time that wave needs to issue it, and the binary64 Box-Muller pairs
+// (a logarithm, a square root, a cosine and a sine per two normals) are a
+// large part of that.  The normals do not depend on the state, so a
+// workgroup is one integrating wave (G orbits: 16 quads or 4 rows) and NW
+// waves that draw those orbits' normals a batch of steps ahead into LDS,
+// double-buffered, with one workgroup barrier per batch.  Each normal comes
+// from the same Philox block (step, orbit id, j / 4) and Box-Muller code as
+// in the single-wave kernels, so the results are bitwise the same.
+constexpr int kStageDoubles = 2048;  // normals of one batch: G orbits x NPO x B steps
+struct Stage64 {
+    double xi[2][kStageDoubles];  // [buffer][step of the batch][orbit of the group][normal]
 };
 
-// Steps of the call (a multiple of the save stride) and batches of them.
-__device__ __forceinline__ int64_t quad_steps(const Coupled64Args& a) { return (a.nsave - 1) * a.stride; }
-
-template <bool PAD, bool MF>
-__device__ __forceinline__ void quad64_integrate(const Coupled64Args& a, int lane, int64_t o0, QuadStage& sh,
-                                                 int64_t nbatch)
+// Normals of the group's G orbits (o0 .. o0 + G - 1, NPO normals each per
+// step) for the steps of batch bi, written by noise wave w (0 .. NW - 1).
+// Item i = step t x block (q, b) of the batch's 512 Philox blocks; lane
+// `lane` of wave w takes i = lane + 64 (w + NW m), m = 0, 1, ...: with G NPO
+// / 4 blocks per step dividing 64, its orbit q and block b are the same for
+// every m, and only the step changes.
+template <int G, int NPO, int NW>
+__device__ __forceinline__ void draw_batches64(const Coupled64Args& a, int w, int lane, int64_t o0, Stage64& sh,
+                                               int64_t nbatch)
 {
-    const int l = lane & 3;
-    const int64_t o = o0 + (lane >> 2);
-    // A quad past the last orbit runs on zeros (whole quads, so no quad_perm
-    // mixes it with a live orbit) and saves nothing.
-    const bool live = o < a.orbits;
-    const int n = PAD ? a.n : 4;
-    const double* __restrict__ p = a.p + (a.p_per_orbit && live ? o * (int64_t)(2 * n + 1) : 0);
-    const int q = a.observable == kKuramotoR ? 1 : n;
-    double* __restrict__ out_row = a.out + (live ? o : 0) * a.nsave * q;
-
-    const bool real = live && (!PAD || l < n);
-    double th = real ? load_phase64(a.X0[o * n + l]) : 0.0;
-    const double drift0 = real ? p[1 + l] * a.dt : 0.0;
-    const double noise = real ? p[1 + n + l] * a.sqdt : 0.0;
-    const double kc = real ? p[0] * (a.dt / (double)n) : 0.0;
-    const double w = real ? 1.0 : 0.0;
-    const double pads = (double)(4 - n);
-
-    auto save = [&](int64_t s) {
-        if (a.observable == kKuramotoR) {
-            const double C = quad_sum64(cos(th) * w), S = quad_sum64(sin(th) * w);
-            const double r = sqrt(C * C + S * S) / (double)n;
-            if (live && l == 0) {
-                note_nonfinite(a.nonfinite, r);
-                out_row[s] = r;
-            }
-        } else if (real) {
-            note_nonfinite(a.nonfinite, th);
-            out_row[s * n + l] = th;
-        }
-    };
-    auto step = [&](double xi) {
-        double acc;
-        if constexpr (MF) {
-            double sn, cs;
-            sincos(th, &sn, &cs);
-            const double C = quad_sum64(cs * w), S = quad_sum64(sn * w);
-            acc = cs * S - sn * C;
-        } else {
-            const double s1 = sin_phase64(quad_perm64<kQuadNext>(th) - th);
-            acc = s1 - quad_perm64<kQuadPrev>(s1);
-            acc += sin_phase64(quad_perm64<kQuadOpp>(th) - th);
-            if constexpr (PAD)
-                acc = fma(pads, sin_phase64(th), acc);
-        }
-        th = wrap64(th + (fma(kc, acc, drift0) + noise * xi));
-    };
-
-    save(0);
-    const int64_t nsteps = quad_steps(a);
-    // Steps left until the next save and the next save's index: the same in
-    // every lane (scalar).
-    int64_t s = 1, to_save = a.stride;
-    for (int64_t bi = 0; bi < nbatch; ++bi) {
-        __syncthreads();  // the noise waves have staged batch bi
-        const double* __restrict__ src = &sh.xi[bi & 1][0][lane];
-        const int64_t k0 = bi * kQuadBatch;
-        if (k0 + kQuadBatch <= nsteps) {
-            double xi = src[0];
-#pragma unroll 4
-            for (int t = 0; t < kQuadBatch; ++t) {
-                const double xn = src[(t + 1 < kQuadBatch ? t + 1 : t) * 64];  // read ahead
-                step(xi);
-                if (--to_save == 0) {
-                    save(s);
-                    ++s;
-                    to_save = a.stride;
-                }
-                xi = xn;
-            }
-        } else {
-            for (int t = 0; k0 + t < nsteps; ++t) {
-                step(src[t * 64]);
-                if (--to_save == 0) {
-                    save(s);
-                    ++s;
-                    to_save = a.stride;
-                }
-            }
-        }
-    }
-}
-
-// Noise wave w (0 .. NW-1): lane = orbit (lane & 15) of the group and step
-// phase (lane >> 4) + 4 w, so the NW waves draw every step of a batch once:
-// one Philox block and its two Box-Muller pairs per orbit and step, the four
-// normals written to the four lanes of the orbit's quad.
-template <int NW>
-__device__ __forceinline__ void quad64_draw(const Coupled64Args& a, int w, int lane, int64_t o0, QuadStage& sh,
-                                            int64_t nbatch)
-{
-    static_assert(kQuadBatch % (4 * NW) == 0, "steps of a batch per noise lane");
-    const int q = lane & 15;
-    const int t0 = (lane >> 4) + 4 * w;
-    // Past the last orbit: the stream of the last one, drawn for lanes that
-    // never save.
+    constexpr int kBlocksPerStep = G * NPO / 4;
+    constexpr int B = kStageDoubles / (G * NPO);
+    constexpr int kItemsPerLane = kBlocksPerStep * B / (64 * NW);
+    static_assert(64 % kBlocksPerStep == 0 && (kBlocksPerStep * B) % (64 * NW) == 0, "noise item mapping");
+    const int rem = lane % kBlocksPerStep;
+    const int q = rem / (NPO / 4);
+    const int b = rem % (NPO / 4);
+    // Past the last orbit: the stream of the last one, for lanes that never save.
     const int64_t o = o0 + q < a.orbits ? o0 + q : a.orbits - 1;
     const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
     auto draw = [&](int64_t bi) {
-        double* __restrict__ dst = &sh.xi[bi & 1][0][4 * q];
-        const uint32_t k0 = (uint32_t)a.step_offset + (uint32_t)(bi * kQuadBatch);
+        double* __restrict__ dst = sh.xi[bi & 1] + q * NPO + 4 * b;
+        const uint32_t k0 = (uint32_t)a.step_offset + (uint32_t)(bi * B);
 #pragma unroll 2
-        for (int i = 0; i < kQuadBatch / (4 * NW); ++i) {
-            const int t = t0 + 4 * NW * i;
-            const Block4 wd = philox_4x32_10(k0 + (uint32_t)t, st.oid, 0u, 0u, st.key_lo, st.key_hi);
+        for (int m = 0; m < kItemsPerLane; ++m) {
+            const int t = (lane + 64 * (w + NW * m)) / kBlocksPerStep;
+            const Block4 wd = philox_4x32_10(k0 + (uint32_t)t, st.oid, (uint32_t)b, 0u, st.key_lo, st.key_hi);
             double z0, z1, z2, z3;
             box_muller_f64_u24(wd.w0, wd.w1, z0, z1);
             box_muller_f64_u24(wd.w2, wd.w3, z2, z3);
-            double* __restrict__ at = dst + t * 64;
+            double* __restrict__ at = dst + t * (G * NPO);
             at[0] = z0;
             at[1] = z1;
             at[2] = z2;
@@ -578,45 +527,84 @@ __device__ __forceinline__ void quad64_draw(const Coupled64Args& a, int w, int l
     for (int64_t bi = 0; bi < nbatch; ++bi) {
         __syncthreads();  // matches the integrating wave's barrier before batch bi
         if (bi + 1 < nbatch)
-            draw(bi + 1);  // the buffer batch bi - 1 used, read before this barrier
+            draw(bi + 1);  // into the buffer batch bi - 1 used, read before this barrier
     }
 }
 
-template <bool PAD, bool MF, int NW>
-__global__ __launch_bounds__(64 * (1 + NW)) void kuramoto_quad64_staged_kernel(const Coupled64Args a)
+template <class Orbit, int G, int NPO, int NW>
+__global__ __launch_bounds__(64 * (1 + NW)) void coupled64_staged_kernel(const Coupled64Args a)
 {
-    __shared__ QuadStage sh;
+    constexpr int P = Orbit::kNormals;
+    constexpr int B = kStageDoubles / (G * NPO);
+    static_assert(G * Orbit::kLanes == 64 && G * NPO == 64 * P, "one integrating wave per group");
+    __shared__ Stage64 sh;
     // Uniform in each wave, so the integrate / draw branch is scalar and
     // every wave reaches the same number of barriers (one per batch).
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int64_t o0 = (int64_t)blockIdx.x * kQuadOrbitsPerGroup;
-    const int64_t nbatch = (quad_steps(a) + kQuadBatch - 1) / kQuadBatch;
-    if (wave == 0)
-        quad64_integrate<PAD, MF>(a, lane, o0, sh, nbatch);
-    else
-        quad64_draw<NW>(a, wave - 1, lane, o0, sh, nbatch);
+    const int64_t o0 = (int64_t)blockIdx.x * G;
+    const int64_t nsteps = (a.nsave - 1) * a.stride;
+    const int64_t nbatch = (nsteps + B - 1) / B;
+    if (wave != 0) {
+        draw_batches64<G, NPO, NW>(a, wave - 1, lane, o0, sh, nbatch);
+        return;
+    }
+    const int64_t o = o0 + lane / Orbit::kLanes;
+    Orbit f(a, o, lane % Orbit::kLanes, o < a.orbits);
+    f.save(a, 0);
+    // Steps left until the next save and the next save's index: the same in
+    // every lane (scalar).
+    int64_t s = 1, to_save = a.stride;
+    for (int64_t bi = 0; bi < nbatch; ++bi) {
+        __syncthreads();  // the noise waves have staged batch bi
+        const double* __restrict__ src = sh.xi[bi & 1] + lane * P;
+        const int64_t k0 = bi * B;
+        if (k0 + B <= nsteps) {
+            double xi[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+                xi[i] = src[i];
+#pragma unroll 4
+            for (int t = 0; t < B; ++t) {
+                double xn[P];  // read ahead
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    xn[i] = src[(t + 1 < B ? t + 1 : t) * (64 * P) + i];
+                f.step(xi);
+                if (--to_save == 0) {
+                    f.save(a, s);
+                    ++s;
+                    to_save = a.stride;
+                }
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    xi[i] = xn[i];
+            }
+        } else {
+            for (int t = 0; k0 + t < nsteps; ++t) {
+                double xi[P];
+#pragma unroll
+                for (int i = 0; i < P; ++i)
+                    xi[i] = src[t * (64 * P) + i];
+                f.step(xi);
+                if (--to_save == 0) {
+                    f.save(a, s);
+                    ++s;
+                    to_save = a.stride;
+                }
+            }
+        }
+    }
 }
 
-template <bool PAD, bool MF>
-hipError_t launch_quad64_staged(const Request& r, const Coupled64Args& a, int nw)
-{
-    const dim3 grid((unsigned)((r.orbits + kQuadOrbitsPerGroup - 1) / kQuadOrbitsPerGroup));
-    if (nw == 2)
-        hipLaunchKernelGGL((kuramoto_quad64_staged_kernel<PAD, MF, 2>), grid, dim3(192), 0, r.stream, a);
-    else
-        hipLaunchKernelGGL((kuramoto_quad64_staged_kernel<PAD, MF, 1>), grid, dim3(128), 0, r.stream, a);
-    return hipGetLastError();
-}
-
-// Noise waves per integrating wave of the four-lane form: the request's
-// choice, or by ensemble size.  Up to two workgroups per compute unit, two
-// (the noise then keeps up with an integrating wave that has a SIMD to
-// itself); up to one integrating wave per SIMD (four per compute unit),
-// one; beyond that none: the SIMDs are shared and the waves of other
-// orbits fill each other's gaps, so moving the normals to other waves only
-// adds their LDS traffic and barriers.
-int quad64_noise_waves(const Request& r)
+// Noise waves per integrating wave of a staged form: the request's choice
+// (the row form stages P = 1, 2, 4 only), or by ensemble size.  Up to two
+// integrating waves per compute unit, two (the noise then keeps up with an
+// integrating wave that has a SIMD to itself); up to one per SIMD (four per
+// compute unit), one; beyond that none: the SIMDs are shared and the waves
+// of other orbits fill each other's gaps, so moving the normals to other
+// waves only adds their LDS traffic and barriers.
+int noise_waves64(const Request& r, int64_t groups)
 {
     if (r.noise_waves >= 0)
         return r.noise_waves;
@@ -624,23 +612,32 @@ int quad64_noise_waves(const Request& r)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    const int64_t groups = (r.orbits + kQuadOrbitsPerGroup - 1) / kQuadOrbitsPerGroup;
     return groups <= 2 * (int64_t)cus ? 2 : groups <= 4 * (int64_t)cus ? 1 : 0;
+}
+
+template <class Orbit, int G, int NPO>
+hipError_t launch_staged64(const Request& r, const Coupled64Args& a, int nw)
+{
+    const dim3 grid((unsigned)((r.orbits + G - 1) / G));
+    if (nw == 2)
+        hipLaunchKernelGGL((coupled64_staged_kernel<Orbit, G, NPO, 2>), grid, dim3(192), 0, r.stream, a);
+    else
+        hipLaunchKernelGGL((coupled64_staged_kernel<Orbit, G, NPO, 1>), grid, dim3(128), 0, r.stream, a);
+    return hipGetLastError();
 }
 
 template <bool PAD>
 hipError_t launch_quad64(const Request& r, const Coupled64Args& a)
 {
-    const int nw = quad64_noise_waves(r);
+    const int nw = noise_waves64(r, (r.orbits + 15) / 16);
     if (nw > 0)
-        return r.drift == 1 ? launch_quad64_staged<PAD, true>(r, a, nw) : launch_quad64_staged<PAD, false>(r, a, nw);
-    const int64_t threads = r.orbits * 4;
-    const dim3 block(256);
-    const dim3 grid((unsigned)((threads + 255) / 256));
+        return r.drift == 1 ? launch_staged64<QuadOrbit64<PAD, true>, 16, 4>(r, a, nw)
+                            : launch_staged64<QuadOrbit64<PAD, false>, 16, 4>(r, a, nw);
+    const dim3 grid((unsigned)((r.orbits * 4 + 255) / 256));
     if (r.drift == 1)
-        hipLaunchKernelGGL((kuramoto_quad64_kernel<PAD, true>), grid, block, 0, r.stream, a);
+        hipLaunchKernelGGL((kuramoto_quad64_kernel<PAD, true>), grid, dim3(256), 0, r.stream, a);
     else
-        hipLaunchKernelGGL((kuramoto_quad64_kernel<PAD, false>), grid, block, 0, r.stream, a);
+        hipLaunchKernelGGL((kuramoto_quad64_kernel<PAD, false>), grid, dim3(256), 0, r.stream, a);
     return hipGetLastError();
 }
 
@@ -667,13 +664,17 @@ hipError_t launch_p64(const Request& r)
     a.nonfinite = r.nonfinite;
     if (P == 1 && r.n <= 4)  // four lanes per orbit
         return r.n == 4 ? launch_quad64<false>(r, a) : launch_quad64<true>(r, a);
-    const int64_t threads = r.orbits * 16;
-    const dim3 block(256);
-    const dim3 grid((unsigned)((threads + 255) / 256));
+    if constexpr (P == 1 || P == 2 || P == 4) {
+        const int nw = noise_waves64(r, (r.orbits + 3) / 4);
+        if (nw > 0)
+            return r.drift == 1 ? launch_staged64<RowOrbit64<P, PAD, true>, 4, 16 * P>(r, a, nw)
+                                : launch_staged64<RowOrbit64<P, PAD, false>, 4, 16 * P>(r, a, nw);
+    }
+    const dim3 grid((unsigned)((r.orbits * 16 + 255) / 256));
     if (r.drift == 1)
-        hipLaunchKernelGGL((kuramoto_coupled64_kernel<P, PAD, true>), grid, block, 0, r.stream, a);
+        hipLaunchKernelGGL((kuramoto_coupled64_kernel<P, PAD, true>), grid, dim3(256), 0, r.stream, a);
     else
-        hipLaunchKernelGGL((kuramoto_coupled64_kernel<P, PAD, false>), grid, block, 0, r.stream, a);
+        hipLaunchKernelGGL((kuramoto_coupled64_kernel<P, PAD, false>), grid, dim3(256), 0, r.stream, a);
     return hipGetLastError();
 }
 

@@ -84,14 +84,18 @@ def test_quad_form_auto_selection_and_shards(gpu):
 
 
 @pytest.mark.parametrize("n,obs,drift", [(4, "state", 0), (3, "kuramoto_r", 0), (2, "state", 1),
-                                         (1, "kuramoto_r", 1)])
-def test_quad_form_noise_waves_bitwise(gpu, n, obs, drift):
-    """The four-lane form with its normals drawn by one or two other waves
-    of the workgroup into LDS ("noise_waves" 1, 2) gives the bits of the
-    lanes drawing their own (0): the same Philox blocks, the same binary64
-    Box-Muller code.  77 orbits (a partial 16-orbit group), 1001 steps (a
-    partial 32-step batch), a non-zero step offset; one case also against
-    the oracle, and a call with no steps (only the initial save)."""
+                                         (1, "kuramoto_r", 1), (16, "state", 0), (7, "kuramoto_r", 1),
+                                         (32, "state", 0), (20, "kuramoto_r", 0), (64, "kuramoto_r", 0),
+                                         (50, "state", 1)])
+def test_noise_waves_bitwise(gpu, n, obs, drift):
+    """The four-lane form (n <= 4) and the 16-lane rows with one, two or
+    four oscillators per lane (padded and not) with their normals drawn by
+    one or two other waves of the workgroup into LDS ("noise_waves" 1, 2)
+    give the bits of the lanes drawing their own (0): the same Philox
+    blocks, the same binary64 Box-Muller code.  77 orbits (partial groups of
+    16 quads or 4 rows), 1001 steps (partial batches of 32, 16 or 8 steps),
+    a non-zero step offset; n = 4 and n = 32 also against the oracle, and a
+    call with no steps (only the initial save)."""
     rng = np.random.default_rng(90 + n)
     orbits = 77
     X0 = rng.uniform(-np.pi, np.pi, (orbits, n))
@@ -101,16 +105,16 @@ def test_quad_form_noise_waves_bitwise(gpu, n, obs, drift):
              stride=143, seed=78, observable=obs)
     res = {}
     for nw in (0, 1, 2):
-        log(f"coupled fp64 quad n={n} {obs} drift={drift} noise_waves={nw}")
+        log(f"coupled fp64 n={n} {obs} drift={drift} noise_waves={nw}")
         res[nw] = run_library(w, precision=64, kernel="coupled", drift=drift, noise_waves=nw,
                               step_offset=5000)
     np.testing.assert_array_equal(res[1], res[0])
     np.testing.assert_array_equal(res[2], res[0])
-    if n == 4:
+    if n in (4, 32):
         want = run_oracle(w, step_offset=5000)
         assert circular_diff(res[1], want).max() <= 1e-10
     for nw in (0, 1, 2):
-        log(f"coupled fp64 quad n={n} no steps noise_waves={nw}")
+        log(f"coupled fp64 n={n} no steps noise_waves={nw}")
         got = run_library(w, precision=64, kernel="coupled", drift=drift, noise_waves=nw, nsteps=0)
         want = run_library(w, precision=64, kernel="plain", drift=drift, nsteps=0)
         np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
