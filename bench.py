@@ -473,7 +473,8 @@ def grid_fp64_leg(sode, torch, w, X0, p, dev, bsteps: int, rows, ref_rows=None) 
         it = sode.Integrator("kuramoto", n, n, 2 * n + 1, precision=64, observable="kuramoto_r",
                              kernel=kernel)
         out = torch.empty((orbits, bsteps // stride + 1, 1), dtype=torch.float64, device=dev)
-        it.integrate(X64[:256], p64[:256], 0.0, w["dt"], stride, stride, w["seed"])
+        # Warm-up on the whole ensemble (the kernel choice depends on the orbit count).
+        it.integrate(X64, p64, 0.0, w["dt"], stride, stride, w["seed"])
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
