@@ -1,21 +1,23 @@
 // kuramoto_coupled64.hip - binary64 Euler-Maruyama integration of stochastic
-// Kuramoto networks (Eq. 5/6 of Sec. 2.2.1), 16 lanes per orbit.
+// Kuramoto networks (Eq. 5/6 of Sec. 2.2.1), 16 or 4 lanes per orbit.
 //
 // The binary64 counterpart of kuramoto_coupled.hip, for the precision the
 // paper measured in (Sec. 2.2.1): lane l of a 16-lane DPP row owns the
 // P = ceil(N/16) oscillators P*l .. P*l+P-1 (rows of N < 16P padded with
 // oscillators frozen at phase 0 whose terms are cancelled, as in the binary32
-// kernel); every unordered pair {i, j} is evaluated once, with a binary64
-// sine for the bounded arguments these phases give (sin_phase64), and used
-// for both oscillators; 64-bit values cross
-// lanes as two 32-bit DPP row rotations.  The state is kept in radians and
-// wrapped to [-pi, pi] every step (theta - k 2pi_hi - k 2pi_lo, no rounding
-// when k = 0).  Normals come from the same Philox blocks and uniforms as the
-// plain kernel's and the oracle's, through a Box-Muller pair that uses that
-// the uniforms are 24-bit (box_muller_f64_u24: within a few ulp of the
-// device library's functions, at well under half their issue cost).  Compared with one orbit per lane it moves 16x
-// more lanes through each step, which matters when the ensemble is too
-// small to fill the chip (Sec. 2.2.1 starts at 512 orbits).
+// kernel); for N <= 4 a quad of lanes holds the orbit instead.  Every
+// unordered pair {i, j} is evaluated once, with a binary64 sine for the
+// bounded arguments these phases give (sin_phase64), and used for both
+// oscillators; 64-bit values cross lanes as two 32-bit DPP moves.  The state
+// is kept in radians and wrapped to [-pi, pi] every step (theta - k 2pi_hi -
+// k 2pi_lo, no rounding when k = 0).  Normals come from the same Philox
+// blocks and uniforms as the plain kernel's and the oracle's, through a
+// Box-Muller pair that uses that the uniforms are 24-bit (box_muller_f64_u24:
+// within a few ulp of the device library's functions, at about 70 % of their
+// issue cost); for small ensembles other waves of the workgroup draw them.
+// Compared with one orbit per lane it moves 16x (4x) more lanes through each
+// step, which matters when the ensemble is too small to fill the chip (Sec.
+// 2.2.1 starts at 512 orbits).
 #include "devmath.hpp"
 #include "launch.hpp"
 #include "noise.hpp"
