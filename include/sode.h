@@ -170,8 +170,9 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  selects it, "kernel" 2 and sode_forward_ckpt /
  *                  sode_adjoint give SODE_EUNSUPPORTED.  Other models
  *                  ignore the option.
- *   "noise_waves"  binary64 coupled Kuramoto kernel (four lanes per orbit
- *                  for n <= 4, 16-lane rows for n <= 32 and 49 <= n <= 64):
+ *   "noise_waves"  coupled Kuramoto kernels (binary64: four lanes per orbit
+ *                  for n <= 4, 16-lane rows for n <= 32 and 49 <= n <= 64;
+ *                  binary32: 16-lane rows for n <= 32 and 49 <= n <= 64):
  *                  0 = every lane draws its own normals; 1 or 2 = each
  *                  workgroup is one integrating wave (16 quads or 4 rows)
  *                  and that many waves drawing their normals a batch of
@@ -181,7 +182,7 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  two integrating waves per compute unit, 1 while there
  *                  are at most four, else 0.  The normals, and so the
  *                  results, are bitwise the same in every case.  Other
- *                  kernels (and rows of 33 <= n <= 48) ignore the option.
+ *                  kernels and row sizes ignore the option.
  *   "observable"   0 = state (q = n values per save);
  *                  1 = Kuramoto order parameter r of Eq. (7), Sec. 2.3.1
  *                      (q = 1; Kuramoto only).

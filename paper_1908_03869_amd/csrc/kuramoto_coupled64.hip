@@ -21,6 +21,7 @@
 #include "devmath.hpp"
 #include "launch.hpp"
 #include "noise.hpp"
+#include "noise_stage.hpp"
 #include "phase64.hpp"
 
 namespace sode {
@@ -472,149 +473,13 @@ __global__ __launch_bounds__(256) void kuramoto_quad64_kernel(const Coupled64Arg
     }
 }
 
-// The same forms with their normals drawn by other waves.  An ensemble too
-// small to fill the chip leaves one wave alone on its SIMD, so a step costs
-// the time that wave needs to issue it, and the binary64 Box-Muller pairs
-// (a logarithm, a square root, a cosine and a sine per two normals) are a
-// large part of that.  The normals do not depend on the state, so a
-// workgroup is one integrating wave (G orbits: 16 quads or 4 rows) and NW
-// waves that draw those orbits' normals a batch of steps ahead into LDS,
-// double-buffered, with one workgroup barrier per batch.  Each normal comes
-// from the same Philox block (step, orbit id, j / 4) and Box-Muller code as
-// in the single-wave kernels, so the results are bitwise the same.
-constexpr int kStageDoubles = 2048;  // normals of one batch: G orbits x NPO x B steps
-struct Stage64 {
-    double xi[2][kStageDoubles];  // [buffer][step of the batch][orbit of the group][normal]
-};
-
-// Normals of the group's G orbits (o0 .. o0 + G - 1, NPO normals each per
-// step) for the steps of batch bi, written by noise wave w (0 .. NW - 1).
-// Item i = step t x block (q, b) of the batch's 512 Philox blocks; lane
-// `lane` of wave w takes i = lane + 64 (w + NW m), m = 0, 1, ...: with G NPO
-// / 4 blocks per step dividing 64, its orbit q and block b are the same for
-// every m, and only the step changes.
-template <int G, int NPO, int NW>
-__device__ __forceinline__ void draw_batches64(const Coupled64Args& a, int w, int lane, int64_t o0, Stage64& sh,
-                                               int64_t nbatch)
-{
-    constexpr int kBlocksPerStep = G * NPO / 4;
-    constexpr int B = kStageDoubles / (G * NPO);
-    constexpr int kItemsPerLane = kBlocksPerStep * B / (64 * NW);
-    static_assert(64 % kBlocksPerStep == 0 && (kBlocksPerStep * B) % (64 * NW) == 0, "noise item mapping");
-    const int rem = lane % kBlocksPerStep;
-    const int q = rem / (NPO / 4);
-    const int b = rem % (NPO / 4);
-    // Past the last orbit: the stream of the last one, for lanes that never save.
-    const int64_t o = o0 + q < a.orbits ? o0 + q : a.orbits - 1;
-    const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
-    auto draw = [&](int64_t bi) {
-        double* __restrict__ dst = sh.xi[bi & 1] + q * NPO + 4 * b;
-        const uint32_t k0 = (uint32_t)a.step_offset + (uint32_t)(bi * B);
-#pragma unroll 2
-        for (int m = 0; m < kItemsPerLane; ++m) {
-            const int t = (lane + 64 * (w + NW * m)) / kBlocksPerStep;
-            const Block4 wd = philox_4x32_10(k0 + (uint32_t)t, st.oid, (uint32_t)b, 0u, st.key_lo, st.key_hi);
-            double z0, z1, z2, z3;
-            box_muller_f64_u24(wd.w0, wd.w1, z0, z1);
-            box_muller_f64_u24(wd.w2, wd.w3, z2, z3);
-            double* __restrict__ at = dst + t * (G * NPO);
-            at[0] = z0;
-            at[1] = z1;
-            at[2] = z2;
-            at[3] = z3;
-        }
-    };
-    if (nbatch > 0)
-        draw(0);
-    for (int64_t bi = 0; bi < nbatch; ++bi) {
-        __syncthreads();  // matches the integrating wave's barrier before batch bi
-        if (bi + 1 < nbatch)
-            draw(bi + 1);  // into the buffer batch bi - 1 used, read before this barrier
-    }
-}
-
+// The same forms with their normals drawn by other waves of the workgroup
+// (noise_stage.hpp): one integrating wave of G orbits (16 quads or 4 rows).
 template <class Orbit, int G, int NPO, int NW>
 __global__ __launch_bounds__(64 * (1 + NW)) void coupled64_staged_kernel(const Coupled64Args a)
 {
-    constexpr int P = Orbit::kNormals;
-    constexpr int B = kStageDoubles / (G * NPO);
-    static_assert(G * Orbit::kLanes == 64 && G * NPO == 64 * P, "one integrating wave per group");
-    __shared__ Stage64 sh;
-    // Uniform in each wave, so the integrate / draw branch is scalar and
-    // every wave reaches the same number of barriers (one per batch).
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int64_t o0 = (int64_t)blockIdx.x * G;
-    const int64_t nsteps = (a.nsave - 1) * a.stride;
-    const int64_t nbatch = (nsteps + B - 1) / B;
-    if (wave != 0) {
-        draw_batches64<G, NPO, NW>(a, wave - 1, lane, o0, sh, nbatch);
-        return;
-    }
-    const int64_t o = o0 + lane / Orbit::kLanes;
-    Orbit f(a, o, lane % Orbit::kLanes, o < a.orbits);
-    f.save(a, 0);
-    // Steps left until the next save and the next save's index: the same in
-    // every lane (scalar).
-    int64_t s = 1, to_save = a.stride;
-    for (int64_t bi = 0; bi < nbatch; ++bi) {
-        __syncthreads();  // the noise waves have staged batch bi
-        const double* __restrict__ src = sh.xi[bi & 1] + lane * P;
-        const int64_t k0 = bi * B;
-        if (k0 + B <= nsteps) {
-            double xi[P];
-#pragma unroll
-            for (int i = 0; i < P; ++i)
-                xi[i] = src[i];
-#pragma unroll 4
-            for (int t = 0; t < B; ++t) {
-                double xn[P];  // read ahead
-#pragma unroll
-                for (int i = 0; i < P; ++i)
-                    xn[i] = src[(t + 1 < B ? t + 1 : t) * (64 * P) + i];
-                f.step(xi);
-                if (--to_save == 0) {
-                    f.save(a, s);
-                    ++s;
-                    to_save = a.stride;
-                }
-#pragma unroll
-                for (int i = 0; i < P; ++i)
-                    xi[i] = xn[i];
-            }
-        } else {
-            for (int t = 0; k0 + t < nsteps; ++t) {
-                double xi[P];
-#pragma unroll
-                for (int i = 0; i < P; ++i)
-                    xi[i] = src[t * (64 * P) + i];
-                f.step(xi);
-                if (--to_save == 0) {
-                    f.save(a, s);
-                    ++s;
-                    to_save = a.stride;
-                }
-            }
-        }
-    }
-}
-
-// Noise waves per integrating wave of a staged form: the request's choice
-// (the row form stages P = 1, 2, 4 only), or by ensemble size.  Up to two
-// integrating waves per compute unit, two (the noise then keeps up with an
-// integrating wave that has a SIMD to itself); up to one per SIMD (four per
-// compute unit), one; beyond that none: the SIMDs are shared and the waves
-// of other orbits fill each other's gaps, so moving the normals to other
-// waves only adds their LDS traffic and barriers.
-int noise_waves64(const Request& r, int64_t groups)
-{
-    if (r.noise_waves >= 0)
-        return r.noise_waves;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
-    return groups <= 2 * (int64_t)cus ? 2 : groups <= 4 * (int64_t)cus ? 1 : 0;
+    __shared__ __attribute__((aligned(16))) double stage[2][kStageNormals64];
+    staged_workgroup<Orbit, double, kStageNormals64, G, NPO, NW>(a, stage);
 }
 
 template <class Orbit, int G, int NPO>
@@ -631,7 +496,7 @@ hipError_t launch_staged64(const Request& r, const Coupled64Args& a, int nw)
 template <bool PAD>
 hipError_t launch_quad64(const Request& r, const Coupled64Args& a)
 {
-    const int nw = noise_waves64(r, (r.orbits + 15) / 16);
+    const int nw = staged_noise_waves(r, (r.orbits + 15) / 16);
     if (nw > 0)
         return r.drift == 1 ? launch_staged64<QuadOrbit64<PAD, true>, 16, 4>(r, a, nw)
                             : launch_staged64<QuadOrbit64<PAD, false>, 16, 4>(r, a, nw);
@@ -667,7 +532,7 @@ hipError_t launch_p64(const Request& r)
     if (P == 1 && r.n <= 4)  // four lanes per orbit
         return r.n == 4 ? launch_quad64<false>(r, a) : launch_quad64<true>(r, a);
     if constexpr (P == 1 || P == 2 || P == 4) {
-        const int nw = noise_waves64(r, (r.orbits + 3) / 4);
+        const int nw = staged_noise_waves(r, (r.orbits + 3) / 4);
         if (nw > 0)
             return r.drift == 1 ? launch_staged64<RowOrbit64<P, PAD, true>, 4, 16 * P>(r, a, nw)
                                 : launch_staged64<RowOrbit64<P, PAD, false>, 4, 16 * P>(r, a, nw);

@@ -385,3 +385,28 @@ def test_module_level_integrate_equals_handle(gpu):
                        observable="kuramoto_r").cpu().numpy()
     b = run_library(dict(w, nsteps=300, stride=100), precision=32)
     np.testing.assert_array_equal(a, b.astype(np.float32))
+
+
+@pytest.mark.parametrize("n,obs,comp,drift", [(5, "state", 1, 0), (16, "kuramoto_r", 1, 0),
+                                              (24, "state", 0, 0), (32, "kuramoto_r", 1, 1),
+                                              (64, "state", 1, 0), (60, "kuramoto_r", 0, 1)])
+def test_coupled_fp32_noise_waves_bitwise(gpu, n, obs, comp, drift):
+    """The binary32 16-lane rows (1, 2 or 4 oscillators per lane, padded and
+    not, compensated and not) with their normals drawn by one or two other
+    waves of the workgroup ("noise_waves" 1, 2) give the bits of the rows
+    drawing their own (0): 77 orbits (a partial group of 4 rows), 1001 steps
+    (partial batches of 64, 32 or 16 steps), a non-zero step offset."""
+    rng = np.random.default_rng(300 + n)
+    orbits = 77
+    X0 = rng.uniform(-np.pi, np.pi, (orbits, n))
+    p = workloads.kuramoto_params(rng.uniform(0.0, 4.0, orbits), rng.standard_normal((orbits, n)),
+                                  rng.uniform(0.05, 0.5, (orbits, n)))
+    w = dict(model="kuramoto", n=n, m=n, d=2 * n + 1, X0=X0, p=p, t0=0.0, dt=1e-2, nsteps=1001,
+             stride=143, seed=79, observable=obs)
+    res = {}
+    for nw in (0, 1, 2):
+        log(f"coupled fp32 n={n} {obs} comp={comp} drift={drift} noise_waves={nw}")
+        res[nw] = run_library(w, precision=32, kernel="coupled", compensated=comp, drift=drift,
+                              noise_waves=nw, step_offset=5000)
+    np.testing.assert_array_equal(res[1], res[0])
+    np.testing.assert_array_equal(res[2], res[0])
