@@ -293,7 +293,7 @@ __device__ __forceinline__ void integrate_group(const RaggedKernelArgs& a, int32
                 float xn[U];
                 load_xi(src, t + 1 < B ? t + 1 : t, xn);  // read ahead, off the update's path
                 advance(xi);
-                if (--to_save == 0) {
+                if (__builtin_expect(--to_save == 0, 0)) {
                     save();
                     to_save = stride;
                 }

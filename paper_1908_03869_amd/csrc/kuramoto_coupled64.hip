@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64
                 if (t == 0 || j + t < nsteps) {
                     f.step(xb[t]);
                     ++k;
-                    if (--to_save == 0) {
+                    if (__builtin_expect(--to_save == 0, 0)) {
                         f.save(a, s);
                         ++s;
                         to_save = a.stride;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) void kuramoto_quad64_kernel(const Coupled64Arg
             if (t == 0 || j + t < nsteps) {
                 f.step(xb[t]);
                 ++k;
-                if (--to_save == 0) {
+                if (__builtin_expect(--to_save == 0, 0)) {
                     f.save(a, s);
                     ++s;
                     to_save = a.stride;

@@ -117,7 +117,7 @@ __device__ __forceinline__ void integrate_staged(const Args& a, Orbit& f, int la
                 for (int i = 0; i < P; ++i)
                     xn[i] = src[(t + 1 < B ? t + 1 : t) * (64 * P) + i];
                 f.step(xi);
-                if (--to_save == 0) {
+                if (__builtin_expect(--to_save == 0, 0)) {
                     f.save(a, s);
                     ++s;
                     to_save = a.stride;
@@ -133,7 +133,7 @@ __device__ __forceinline__ void integrate_staged(const Args& a, Orbit& f, int la
                 for (int i = 0; i < P; ++i)
                     xi[i] = src[t * (64 * P) + i];
                 f.step(xi);
-                if (--to_save == 0) {
+                if (__builtin_expect(--to_save == 0, 0)) {
                     f.save(a, s);
                     ++s;
                     to_save = a.stride;
