@@ -105,16 +105,26 @@ __device__ __forceinline__ void coupling_sums64(const double (&th)[P], double (&
         }
     }
     couple_across64<P, 1>(th, acc);
-    double other[P];
+    // Opposite lane (rotation by 8, its own inverse): pairs (own a, partner
+    // b) with a < b here, returned to the partner, which covers a > b; a = b
+    // by both lanes, each for its own side.
+    double other[P], back[P];
 #pragma unroll
     for (int b = 0; b < P; ++b)
         other[b] = row_rotate64<8>(th[b]);
 #pragma unroll
     for (int a = 0; a < P; ++a) {
 #pragma unroll
-        for (int b = 0; b < P; ++b)
-            acc[a] += sin_phase64(other[b] - th[a]);
+        for (int b = a; b < P; ++b) {
+            const double s = sin_phase64(other[b] - th[a]);
+            acc[a] += s;
+            if (b > a)
+                back[b] = a == 0 ? s : back[b] + s;
+        }
     }
+#pragma unroll
+    for (int b = 1; b < P; ++b)
+        acc[b] -= row_rotate64<8>(back[b]);
 }
 
 // Binary64 normals P*l .. P*l+P-1 of one orbit at global step k: the Philox

@@ -25,8 +25,11 @@
 // use registers; a pair between lane l and lane l' = l (+/-) k (k = 1..7)
 // is evaluated by one of the two lanes, which reads the partner's phases
 // with a DPP row rotation and returns the negated partial sums with the
-// inverse rotation; for k = 8 both lanes evaluate their own side.  Per
-// orbit-step this is N(N-1)/2 + N^2/32 sines instead of N^2.
+// inverse rotation.  For k = 8 (the opposite lane, a rotation that is its
+// own inverse) lane l evaluates its oscillator a against the partner's b for
+// a < b only, the partner covering a > b the same way, and both lanes
+// evaluate a = b, each for its own side.  Per orbit-step this is
+// N(N-1)/2 + N/2 = N^2/2 sines instead of N^2.
 //
 // Noise: lane l needs normals P*l .. P*l+P-1 (lane_normals, noise.hpp).
 //
@@ -136,15 +139,25 @@ __device__ __forceinline__ void coupling_sums(const float (&phi)[P], float (&acc
         }
     }
     couple_rotations<P, 1>(phi, acc);
-    // Opposite lane (rotation by 8 is its own inverse): each side adds its own,
-    // partner phase by partner phase as above.
+    // Opposite lane (rotation by 8 is its own inverse).  Pairs (own a,
+    // partner b) with a < b are evaluated here and returned to the partner,
+    // whose own evaluation covers a > b; a == b (the partner's oscillator of
+    // the same index) is evaluated by both lanes, each for its own side.
+    float back[P];
 #pragma unroll
     for (int b = 0; b < P; ++b) {
         const float other = row_rotate<8>(phi[b]);
 #pragma unroll
-        for (int a = 0; a < P; ++a)
-            acc[a] += sin_rev(other - phi[a]);
+        for (int a = 0; a <= b; ++a) {
+            const float s = sin_rev(other - phi[a]);
+            acc[a] += s;
+            if (a < b)
+                back[b] = a == 0 ? s : back[b] + s;
+        }
     }
+#pragma unroll
+    for (int b = 1; b < P; ++b)
+        acc[b] -= row_rotate<8>(back[b]);
 }
 
 // Sum over the 16 lanes of a row; every lane receives the total.
