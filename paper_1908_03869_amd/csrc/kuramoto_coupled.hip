@@ -12,11 +12,20 @@ namespace {
 
 using namespace coupled32;
 
+// Pairwise rows of P = 2, 4 or 8 oscillators per lane read their partners'
+// phases from LDS (coupling_sums); other rows, and the mean-field form, use
+// DPP only.
+template <int P, bool MF>
+constexpr bool kLdsPhases = !MF && (P == 2 || P == 4 || P == 8);
+
 // One orbit per 16-lane row, P oscillators per lane; PAD: the system has
 // a.n < 16P oscillators and the rest of the row is padding.
 template <int P, bool PAD, bool COMP, bool MF>
 __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs a)
 {
+    constexpr bool LDS = kLdsPhases<P, MF>;
+    __shared__ __attribute__((aligned(16))) float lds_phase[LDS ? 256 * P : 1];
+    float* const row = LDS ? lds_phase + (threadIdx.x & ~15u) * P : nullptr;
     const int l = threadIdx.x & 15;
     const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     // Whole rows are in or out together, so no rotation reads a finished lane.
@@ -52,7 +61,7 @@ __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs
 #pragma unroll
             for (int t = 0; t < B; ++t) {
                 if (t == 0 || j + t < nsteps) {
-                    em_step<P, COMP, MF, PAD>(th, tl, c, st, k, l, nullptr, xb[t]);
+                    em_step<P, COMP, MF, PAD, LDS>(th, tl, c, st, k, l, nullptr, xb[t], row);
                     ++k;
                     if (--to_save == 0) {
                         save<P, PAD>(a, l, th, c, out_row, s);
@@ -65,7 +74,7 @@ __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs
     } else {
         for (int64_t s = 1; s < a.nsave; ++s) {
             for (int64_t kk = 0; kk < a.stride; ++kk, ++k)
-                em_step<P, COMP, MF, PAD>(th, tl, c, st, k, l);
+                em_step<P, COMP, MF, PAD, LDS>(th, tl, c, st, k, l, nullptr, nullptr, row);
             save<P, PAD>(a, l, th, c, out_row, s);
         }
     }

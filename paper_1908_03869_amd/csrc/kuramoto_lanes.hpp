@@ -82,23 +82,82 @@ __device__ __forceinline__ float wrap_rad(float x)
     return __builtin_fmaf(-k, kTwoPiTail, x);
 }
 
-// Pairs between this lane and the lane K rotations away (K = 1..7).
-template <int P, int K>
-__device__ __forceinline__ void couple_across(const float (&phi)[P], float (&acc)[P])
+// Partner phases from LDS (the LDS form of the coupling sums): each lane
+// stores its P scaled phases once per step at row + P l, and reads the P
+// phases of lane (l + K) mod 16 -- the lane row_rotate<16 - K> reads -- with
+// one or two vector loads instead of P subtractions that each carry a DPP
+// operand.  The values, and so the results, are those of the DPP form.
+template <int P>
+__device__ __forceinline__ void lds_store_phases(float* row, int l, const float (&phi)[P])
 {
-    float back[P];
-    // Partner phase b, then its P uses right after it: the compiler folds a
-    // DPP move into its uses (v_sub_f32_dpp) only when they follow within a
-    // few instructions.  Every sum still takes its terms in the same order
-    // (acc[a] over b, back[b] over a).  back[b] starts from its first term
-    // (0 + s is not an identity under IEEE signed zeros, so a zero start
-    // would cost an add per b).
+    if constexpr (P % 4 == 0) {
+#pragma unroll
+        for (int g = 0; g < P / 4; ++g)
+            reinterpret_cast<float4*>(row + P * l)[g] = make_float4(phi[4 * g], phi[4 * g + 1], phi[4 * g + 2], phi[4 * g + 3]);
+    } else if constexpr (P == 2) {
+        *reinterpret_cast<float2*>(row + 2 * l) = make_float2(phi[0], phi[1]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            row[P * l + i] = phi[i];
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void lds_load_phases(const float* row, int lane, float (&out)[P])
+{
+    if constexpr (P % 4 == 0) {
+#pragma unroll
+        for (int g = 0; g < P / 4; ++g) {
+            const float4 v = reinterpret_cast<const float4*>(row + P * lane)[g];
+            out[4 * g] = v.x;
+            out[4 * g + 1] = v.y;
+            out[4 * g + 2] = v.z;
+            out[4 * g + 3] = v.w;
+        }
+    } else if constexpr (P == 2) {
+        const float2 v = *reinterpret_cast<const float2*>(row + 2 * lane);
+        out[0] = v.x;
+        out[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            out[i] = row[P * lane + i];
+    }
+}
+
+// Orders one wave's LDS accesses across its lanes: stores before the loads
+// that follow, loads before the stores that follow.  The LDS serves a
+// wave's operations in order, so this emits no wait; it keeps the compiler
+// from moving the accesses across each other.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pairs between this lane and the lane K rotations away (K = 1..7); LDS:
+// partner phases from the row's copy in LDS (row), else by DPP.
+template <int P, int K, bool LDS>
+__device__ __forceinline__ void couple_across(const float (&phi)[P], float (&acc)[P], const float* row, int l)
+{
+    float back[P], other[P];
+    if constexpr (LDS)
+        lds_load_phases<P>(row, (l + K) & 15, other);
+    // DPP form: partner phase b, then its P uses right after it: the
+    // compiler folds a DPP move into its uses (v_sub_f32_dpp) only when they
+    // follow within a few instructions.  Every sum still takes its terms in
+    // the same order (acc[a] over b, back[b] over a).  back[b] starts from its
+    // first term (0 + s is not an identity under IEEE signed zeros, so a zero
+    // start would cost an add per b).
 #pragma unroll
     for (int b = 0; b < P; ++b) {
-        const float other = row_rotate<16 - K>(phi[b]);
+        if constexpr (!LDS)
+            other[b] = row_rotate<16 - K>(phi[b]);
 #pragma unroll
         for (int a = 0; a < P; ++a) {
-            const float s = sin_rev(other - phi[a]);
+            const float s = sin_rev(other[b] - phi[a]);
             acc[a] += s;
             back[b] = a == 0 ? s : back[b] + s;
         }
@@ -108,18 +167,25 @@ __device__ __forceinline__ void couple_across(const float (&phi)[P], float (&acc
         acc[b] -= row_rotate<K>(back[b]);
 }
 
-template <int P, int K>
-__device__ __forceinline__ void couple_rotations(const float (&phi)[P], float (&acc)[P])
+template <int P, int K, bool LDS>
+__device__ __forceinline__ void couple_rotations(const float (&phi)[P], float (&acc)[P], const float* row, int l)
 {
     if constexpr (K <= 7) {
-        couple_across<P, K>(phi, acc);
-        couple_rotations<P, K + 1>(phi, acc);
+        couple_across<P, K, LDS>(phi, acc, row, l);
+        couple_rotations<P, K + 1, LDS>(phi, acc, row, l);
     }
 }
 
-template <int P>
-__device__ __forceinline__ void coupling_sums(const float (&phi)[P], float (&acc)[P])
+// LDS: partner phases through row (16 P floats of LDS for this lane's row,
+// aligned to 16 bytes), else by DPP row rotations.
+template <int P, bool LDS = false>
+__device__ __forceinline__ void coupling_sums(const float (&phi)[P], float (&acc)[P], float* row = nullptr,
+                                              int l = 0)
 {
+    if constexpr (LDS) {
+        lds_store_phases<P>(row, l, phi);
+        wave_lds_sync();
+    }
     // Pairs inside the lane.  Each sum starts from its first term (with
     // P = 1 there is none and the sums start at 0); the pair order and thus
     // the rounding are those of a zero start.
@@ -138,18 +204,23 @@ __device__ __forceinline__ void coupling_sums(const float (&phi)[P], float (&acc
             }
         }
     }
-    couple_rotations<P, 1>(phi, acc);
+    couple_rotations<P, 1, LDS>(phi, acc, row, l);
     // Opposite lane (rotation by 8 is its own inverse).  Pairs (own a,
     // partner b) with a < b are evaluated here and returned to the partner,
     // whose own evaluation covers a > b; a == b (the partner's oscillator of
     // the same index) is evaluated by both lanes, each for its own side.
-    float back[P];
+    float back[P], other[P];
+    if constexpr (LDS) {
+        lds_load_phases<P>(row, (l + 8) & 15, other);
+        wave_lds_sync();  // every lane's loads before the next step's stores
+    }
 #pragma unroll
     for (int b = 0; b < P; ++b) {
-        const float other = row_rotate<8>(phi[b]);
+        if constexpr (!LDS)
+            other[b] = row_rotate<8>(phi[b]);
 #pragma unroll
         for (int a = 0; a <= b; ++a) {
-            const float s = sin_rev(other - phi[a]);
+            const float s = sin_rev(other[b] - phi[a]);
             acc[a] += s;
             if (a < b)
                 back[b] = a == 0 ? s : back[b] + s;
@@ -244,11 +315,12 @@ __device__ __forceinline__ void mean_field_sums(const float (&phi)[P], float (&a
 // (Fast2Sum), and a wrap moves the tail of 2 pi into tl.  MF: coupling through the
 // mean-field identity instead of pairwise sines.  PAD: see the top of the file.
 // xi_out (optional) receives the step's P normals; xi_in (optional) supplies
-// them, already drawn (lane_normals_steps), instead of lane_normals.
-template <int P, bool COMP, bool MF = false, bool PAD = false>
+// them, already drawn (lane_normals_steps), instead of lane_normals.  LDS:
+// pairwise partner phases through `row` (coupling_sums); the same results.
+template <int P, bool COMP, bool MF = false, bool PAD = false, bool LDS = false>
 __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const LaneCoefficients<P, PAD>& c,
                                         const Stream& st, uint32_t k, int l, float* xi_out = nullptr,
-                                        const float* xi_in = nullptr)
+                                        const float* xi_in = nullptr, float* row = nullptr)
 {
     float phi[P], acc[P], xi[P];
 #pragma unroll
@@ -257,7 +329,7 @@ __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const La
     if constexpr (MF) {
         mean_field_sums<P, PAD>(phi, acc, c);
     } else {
-        coupling_sums<P>(phi, acc);
+        coupling_sums<P, LDS>(phi, acc, row, l);
         if constexpr (PAD) {
 #pragma unroll
             for (int i = 0; i < P; ++i)
