@@ -12,18 +12,13 @@ namespace {
 
 using namespace coupled32;
 
-// Pairwise rows of P = 2, 4 or 8 oscillators per lane read their partners'
-// phases from LDS (coupling_sums); other rows, and the mean-field form, use
-// DPP only.
-template <int P, bool MF>
-constexpr bool kLdsPhases = !MF && (P == 2 || P == 4 || P == 8);
-
 // One orbit per 16-lane row, P oscillators per lane; PAD: the system has
-// a.n < 16P oscillators and the rest of the row is padding.
-template <int P, bool PAD, bool COMP, bool MF>
+// a.n < 16P oscillators and the rest of the row is padding.  LDS: partner
+// phases through LDS (kLdsPartnerPhases rows only), else by DPP.
+template <int P, bool PAD, bool COMP, bool MF, bool LDS>
 __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs a)
 {
-    constexpr bool LDS = kLdsPhases<P, MF>;
+    static_assert(!LDS || kLdsPartnerPhases<P, MF>, "LDS partner phases for rows of 2, 4 or 8, pairwise");
     __shared__ __attribute__((aligned(16))) float lds_phase[LDS ? 256 * P : 1];
     float* const row = LDS ? lds_phase + (threadIdx.x & ~15u) * P : nullptr;
     const int l = threadIdx.x & 15;
@@ -80,6 +75,24 @@ __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs
     }
 }
 
+template <int P, bool PAD, bool LDS>
+hipError_t launch_rows(const Request& r, const CoupledArgs& a)
+{
+    const bool mf = r.drift == 1;
+    const int64_t threads = r.orbits * 16;
+    const dim3 block(256);
+    const dim3 grid((unsigned)((threads + 255) / 256));
+    if (r.compensated && mf)
+        hipLaunchKernelGGL((kuramoto_coupled_kernel<P, PAD, true, true, false>), grid, block, 0, r.stream, a);
+    else if (r.compensated)
+        hipLaunchKernelGGL((kuramoto_coupled_kernel<P, PAD, true, false, LDS>), grid, block, 0, r.stream, a);
+    else if (mf)
+        hipLaunchKernelGGL((kuramoto_coupled_kernel<P, PAD, false, true, false>), grid, block, 0, r.stream, a);
+    else
+        hipLaunchKernelGGL((kuramoto_coupled_kernel<P, PAD, false, false, LDS>), grid, block, 0, r.stream, a);
+    return hipGetLastError();
+}
+
 template <int P, bool PAD>
 hipError_t launch_p(const Request& r)
 {
@@ -90,19 +103,16 @@ hipError_t launch_p(const Request& r)
         if (nw > 0)
             return launch_staged_f32(r, a, nw);
     }
-    const bool mf = r.drift == 1;
-    const int64_t threads = r.orbits * 16;
-    const dim3 block(256);
-    const dim3 grid((unsigned)((threads + 255) / 256));
-    if (r.compensated && mf)
-        hipLaunchKernelGGL((kuramoto_coupled_kernel<P, PAD, true, true>), grid, block, 0, r.stream, a);
-    else if (r.compensated)
-        hipLaunchKernelGGL((kuramoto_coupled_kernel<P, PAD, true, false>), grid, block, 0, r.stream, a);
-    else if (mf)
-        hipLaunchKernelGGL((kuramoto_coupled_kernel<P, PAD, false, true>), grid, block, 0, r.stream, a);
-    else
-        hipLaunchKernelGGL((kuramoto_coupled_kernel<P, PAD, false, false>), grid, block, 0, r.stream, a);
-    return hipGetLastError();
+    if constexpr (kLdsPartnerPhases<P, false>) {
+        // Partner phases through LDS once the SIMDs hold enough row waves to
+        // hide the loads' latency: from 8 waves per SIMD with 4 oscillators
+        // per lane, from 2 with 2 or 8; with fewer the DPP form is faster.
+        // Either form gives the same results.
+        const int64_t waves_per_simd = r.orbits / (16 * (int64_t)device_compute_units());
+        if (r.drift != 1 && waves_per_simd >= (P == 4 ? 8 : 2))
+            return launch_rows<P, PAD, true>(r, a);
+    }
+    return launch_rows<P, PAD, false>(r, a);
 }
 
 template <int P>

@@ -126,6 +126,12 @@ __device__ __forceinline__ void lds_load_phases(const float* row, int lane, floa
     }
 }
 
+// Rows whose pairwise step reads the partner phases from LDS: 2, 4 or 8
+// oscillators per lane (one or two vector loads per partner lane).  With 3,
+// 5, 6 or 7 the loads are scalar and the DPP form is as fast or faster.
+template <int P, bool MF>
+constexpr bool kLdsPartnerPhases = !MF && (P == 2 || P == 4 || P == 8);
+
 // Orders one wave's LDS accesses across its lanes: stores before the loads
 // that follow, loads before the stores that follow.  The LDS serves a
 // wave's operations in order, so this emits no wait; it keeps the compiler

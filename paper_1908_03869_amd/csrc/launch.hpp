@@ -11,6 +11,16 @@
 
 namespace sode {
 
+// Compute units of the current device (256 if the query fails).
+inline int device_compute_units()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
 // One integrate request, already checked for shape and range.
 struct Request {
     int model;

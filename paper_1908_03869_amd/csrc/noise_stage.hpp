@@ -177,10 +177,7 @@ inline int staged_noise_waves(const Request& r, int64_t groups)
 {
     if (r.noise_waves >= 0)
         return r.noise_waves;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
+    const int cus = device_compute_units();
     return groups <= 2 * (int64_t)cus ? 2 : groups <= 4 * (int64_t)cus ? 1 : 0;
 }
 

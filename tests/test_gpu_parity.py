@@ -410,3 +410,30 @@ def test_coupled_fp32_noise_waves_bitwise(gpu, n, obs, comp, drift):
                               noise_waves=nw, step_offset=5000)
     np.testing.assert_array_equal(res[1], res[0])
     np.testing.assert_array_equal(res[2], res[0])
+
+
+@pytest.mark.parametrize("n,lds_rows,dpp_rows", [(64, 128, 32), (50, 128, 32), (32, 32, 20), (128, 32, 16)])
+def test_coupled_fp32_lds_and_dpp_partner_reads_bitwise(gpu, n, lds_rows, dpp_rows):
+    """The unstaged binary32 rows of 2, 4 or 8 oscillators per lane read
+    their partners' phases from LDS once the SIMDs hold enough row waves
+    (8 per SIMD with 4 oscillators per lane, 2 with 2 or 8) and by DPP
+    below that; both forms take the same values in the same order.  An
+    ensemble of lds_rows x CUs orbits (LDS form) and its first dpp_rows x
+    CUs orbits alone (DPP form, above the staged-rows limit) give the same
+    bits: state, pairwise, compensated and not."""
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    big, small = lds_rows * cus, dpp_rows * cus
+    rng = np.random.default_rng(900 + n)
+    X0 = rng.uniform(-np.pi, np.pi, (big, n))
+    p = workloads.kuramoto_params(rng.uniform(0.0, 4.0, big), rng.standard_normal((big, n)),
+                                  rng.uniform(0.05, 0.5, (big, n)))
+    w = dict(model="kuramoto", n=n, m=n, d=2 * n + 1, X0=X0, p=p, t0=0.0, dt=1e-2, nsteps=300,
+             stride=100, seed=83, observable="state")
+    for comp in (1, 0):
+        log(f"coupled fp32 n={n} comp={comp}: {big} orbits (LDS reads) and {small} (DPP reads)")
+        out_big = run_library(w, precision=32, kernel="coupled", compensated=comp)
+        out_small = run_library(w, precision=32, kernel="coupled", compensated=comp,
+                                X0=X0[:small], p=p[:small])
+        np.testing.assert_array_equal(out_big[:small], out_small)
