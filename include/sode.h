@@ -197,9 +197,8 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  3 = matrix (see "gemm").
  *                  Auto takes coupled for binary32 Kuramoto EM with
  *                  5 <= n <= 128 (n < 5: only up to 65,536 orbits) and for
- *                  binary64 Kuramoto EM with n <= 4 at any size or
- *                  5 <= n <= 16 where it is faster (n >= 10, else up to
- *                  2400 n^2 orbits pairwise or 18,000 n mean-field),
+ *                  binary64 Kuramoto EM with n <= 64 (n = 5: up to 60,000
+ *                  orbits, beyond which one orbit per lane is faster),
  *                  matrix for a supported dense network, else plain.
  *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
  *                  used by every orbit.

@@ -148,13 +148,13 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
         *kernel = 1;
     } else if (coupled_ok && h->precision == 32 && (h->n >= 5 || orbits <= 65536)) {
         *kernel = 2;
-    } else if (coupled_ok && h->precision == 64 &&
-               (h->n <= 4 || (h->n <= 16 && (h->n >= 10 || (h->drift == 1 ? orbits <= 18000 * (int64_t)h->n
-                                                                         : orbits <= 2400 * (int64_t)h->n * h->n))))) {
-        // Binary64, 5 <= n <= 9: a padded 16-lane row costs the same for any
-        // n <= 16 and one orbit per lane ~n^2 (pairwise) or ~n (mean-field)
-        // per orbit-step; the crossovers measured at n = 5 (between 40,960
-        // and 81,920 orbits pairwise, near 90,000 mean-field) scale with that.
+    } else if (coupled_ok && h->precision == 64 && (h->n != 5 || orbits <= 60000)) {
+        // Binary64: four lanes per orbit (n <= 4) or a 16-lane row (6 <= n
+        // <= 64) beat one orbit per lane at every ensemble size measured
+        // (paper protocol, up to 196,608 orbits, pairwise and mean-field).
+        // At n = 5 a row is 11/16 padding and the one-orbit-per-lane kernel,
+        // whose time steps with each whole wave per SIMD, is faster from
+        // 65,536 orbits on (within 3 % of the row where the row wins).
         *kernel = 2;
     } else if (matrix_ok) {
         *kernel = 3;

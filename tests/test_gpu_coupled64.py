@@ -118,3 +118,22 @@ def test_noise_waves_bitwise(gpu, n, obs, drift):
         got = run_library(w, precision=64, kernel="coupled", drift=drift, noise_waves=nw, nsteps=0)
         want = run_library(w, precision=64, kernel="plain", drift=drift, nsteps=0)
         np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("n,orbits,expect", [(6, 98304, "coupled"), (17, 2048, "coupled"),
+                                             (5, 65536, "plain"), (5, 4096, "coupled")])
+def test_auto_selection_binary64(gpu, n, orbits, expect):
+    """Auto selection in binary64 takes the 16-lane row for every n in 6..64
+    at any ensemble size and, at n = 5 (a row of 11 pads), one orbit per lane
+    from 65,536 orbits on: the auto result equals the expected kernel's
+    result bit for bit (the two kernels sum in different orders)."""
+    rng = np.random.default_rng(700 + n)
+    X0 = rng.uniform(-np.pi, np.pi, (orbits, n))
+    p = workloads.kuramoto_params(rng.uniform(0.0, 4.0, orbits), rng.standard_normal((orbits, n)),
+                                  rng.uniform(0.05, 0.5, (orbits, n)))
+    w = dict(model="kuramoto", n=n, m=n, d=2 * n + 1, X0=X0, p=p, t0=0.0, dt=1e-2, nsteps=40,
+             stride=20, seed=31, observable="state")
+    log(f"binary64 auto selection n={n} orbits={orbits}: expect {expect}")
+    auto = run_library(w, precision=64, kernel="auto")
+    want = run_library(w, precision=64, kernel=expect)
+    np.testing.assert_array_equal(auto, want)
