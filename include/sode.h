@@ -196,7 +196,9 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  4 lanes per orbit and DPP quad permutations instead);
  *                  3 = matrix (see "gemm").
  *                  Auto takes coupled for binary32 Kuramoto EM with
- *                  5 <= n <= 128 (n < 5: only up to 65,536 orbits) and for
+ *                  n <= 128 (n <= 5: up to 25,000 / 50,000 / 90,000 /
+ *                  100,000 / 200,000 orbits for n = 1..5 on 256 compute
+ *                  units, scaled with the device's) and for
  *                  binary64 Kuramoto EM with n <= 64 (n = 5: up to 60,000
  *                  orbits, beyond which one orbit per lane is faster),
  *                  matrix for a supported dense network, else plain.

@@ -93,19 +93,29 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
     return SODE_OK;
 }
 
+// Largest binary32 Kuramoto ensemble (n <= 5) for which the 16-lane row, a
+// padded one, beats one orbit per lane: the row costs the same per orbit for
+// any n <= 16, while one orbit per lane takes a fixed, latency-bound time
+// until the ensemble fills the chip and ~n^2 per orbit-step after.  Paper
+// protocol (8000 steps) on 256 compute units, scaled with the device's:
+// n = 1 one orbit per lane from 32,768 orbits on (6.5 against 8.7 ms), n = 2
+// from 65,536 (14.0 against 17.0), n = 3 and 4 from 131,072, n = 5 at
+// 262,144 (61.7 against 67.2); from n = 6 the row wins at every size.
+int64_t coupled32_max_orbits(int n)
+{
+    static const int64_t kMax256[6] = {0, 25000, 50000, 90000, 100000, 200000};
+    if (n >= 6)
+        return INT64_MAX;
+    return kMax256[n] * sode::device_compute_units() / 256;
+}
+
 // Which kernel a request goes to; SODE_EUNSUPPORTED if none can run it.
-// Auto follows the paper's speed protocol as measured here (N = 5, 10, 15,
-// 512 to 163,840 orbits).  Binary32: the 16-lane Kuramoto kernel wherever
-// it applies, except for fewer than 5 oscillators over many orbits, where a
-// padded row wastes most of its lanes and one orbit per lane fills the chip
-// anyway (at n = 5 the 16-lane row is faster at every size measured).
-// Binary64, n <= 4: the four-lane form of the coupled kernel at any size (2
-// sines per lane-step, 8 per orbit-step against the 16 of one orbit per
-// lane).  Binary64, 5 <= n <= 16: the 16-lane kernel from n = 10 at any size
-// and below that up to 400 n^2 orbits pairwise (one orbit per lane costs
-// ~n^2 per orbit-step, the padded row a constant; crossover between 5,120 and
-// 25,600 orbits at n = 5) or 65,536 orbits mean-field (crossover between
-// 40,960 and 81,920 at n = 5); otherwise one orbit per lane.
+// Auto follows the paper's speed protocol as measured here.  Binary32: the
+// 16-lane Kuramoto kernel up to coupled32_max_orbits(n), else one orbit per
+// lane.  Binary64: four lanes per orbit for n <= 4 and the 16-lane row for
+// 6 <= n <= 64 at any size; at n = 5 (a row of 11 pads) the row up to 60,000
+// orbits, one orbit per lane beyond.  The dense network goes to the matrix
+// kernel; everything else to one orbit per lane.
 int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 {
     // RK4 and the implicit steppers integrate the ODE limit g = 0.  A model
@@ -146,7 +156,7 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
         if (!plain_ok)
             return SODE_EUNSUPPORTED;
         *kernel = 1;
-    } else if (coupled_ok && h->precision == 32 && (h->n >= 5 || orbits <= 65536)) {
+    } else if (coupled_ok && h->precision == 32 && orbits <= coupled32_max_orbits(h->n)) {
         *kernel = 2;
     } else if (coupled_ok && h->precision == 64 && (h->n != 5 || orbits <= 60000)) {
         // Binary64: four lanes per orbit (n <= 4) or a 16-lane row (6 <= n

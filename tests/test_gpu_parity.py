@@ -437,3 +437,26 @@ def test_coupled_fp32_lds_and_dpp_partner_reads_bitwise(gpu, n, lds_rows, dpp_ro
         out_small = run_library(w, precision=32, kernel="coupled", compensated=comp,
                                 X0=X0[:small], p=p[:small])
         np.testing.assert_array_equal(out_big[:small], out_small)
+
+
+@pytest.mark.parametrize("n,orbits_per_cu,expect", [(1, 128, "plain"), (2, 256, "plain"), (4, 256, "coupled"),
+                                                    (5, 1024, "plain"), (6, 1024, "coupled"), (2, 64, "coupled")])
+def test_auto_selection_binary32(gpu, n, orbits_per_cu, expect):
+    """Binary32 auto selection: the 16-lane row for n >= 6 at any size and
+    for n <= 5 up to a measured ensemble size (25,000 / 50,000 / 90,000 /
+    100,000 / 200,000 orbits for n = 1..5 on 256 compute units, scaled with
+    the device's), else one orbit per lane.  The auto result equals the
+    expected kernel's result bit for bit."""
+    import torch
+
+    orbits = orbits_per_cu * torch.cuda.get_device_properties(0).multi_processor_count
+    rng = np.random.default_rng(600 + n)
+    X0 = rng.uniform(-np.pi, np.pi, (orbits, n))
+    p = workloads.kuramoto_params(rng.uniform(0.0, 4.0, orbits), rng.standard_normal((orbits, n)),
+                                  rng.uniform(0.05, 0.5, (orbits, n)))
+    w = dict(model="kuramoto", n=n, m=n, d=2 * n + 1, X0=X0, p=p, t0=0.0, dt=1e-2, nsteps=40,
+             stride=20, seed=37, observable="state")
+    log(f"binary32 auto selection n={n} orbits={orbits}: expect {expect}")
+    auto = run_library(w, precision=32, kernel="auto")
+    want = run_library(w, precision=32, kernel=expect)
+    np.testing.assert_array_equal(auto, want)
