@@ -420,11 +420,13 @@ def test_coupled_fp32_lds_and_dpp_partner_reads_bitwise(gpu, n, lds_rows, dpp_ro
     below that; both forms take the same values in the same order.  An
     ensemble of lds_rows x CUs orbits (LDS form) and its first dpp_rows x
     CUs orbits alone (DPP form, above the staged-rows limit) give the same
-    bits: state, pairwise, compensated and not."""
+    bits: state, pairwise, compensated and not.  The big ensemble ends in a
+    partial wave (3 orbits past a multiple of 4), whose orbits must equal a
+    run of those orbits alone (orbit_offset keeps their noise streams)."""
     import torch
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    big, small = lds_rows * cus, dpp_rows * cus
+    big, small = lds_rows * cus + 3, dpp_rows * cus
     rng = np.random.default_rng(900 + n)
     X0 = rng.uniform(-np.pi, np.pi, (big, n))
     p = workloads.kuramoto_params(rng.uniform(0.0, 4.0, big), rng.standard_normal((big, n)),
@@ -437,6 +439,9 @@ def test_coupled_fp32_lds_and_dpp_partner_reads_bitwise(gpu, n, lds_rows, dpp_ro
         out_small = run_library(w, precision=32, kernel="coupled", compensated=comp,
                                 X0=X0[:small], p=p[:small])
         np.testing.assert_array_equal(out_big[:small], out_small)
+        out_tail = run_library(w, precision=32, kernel="coupled", compensated=comp,
+                               X0=X0[big - 3:], p=p[big - 3:], orbit_offset=big - 3)
+        np.testing.assert_array_equal(out_big[big - 3:], out_tail)
 
 
 @pytest.mark.parametrize("n,orbits_per_cu,expect", [(1, 128, "plain"), (2, 256, "plain"), (4, 256, "coupled"),
