@@ -197,10 +197,11 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  3 = matrix (see "gemm").
  *                  Auto takes coupled for binary32 Kuramoto EM with
  *                  n <= 128 (n <= 5: up to 25,000 / 50,000 / 90,000 /
- *                  100,000 / 200,000 orbits for n = 1..5 on 256 compute
+ *                  60,000 / 120,000 orbits for n = 1..5 on 256 compute
  *                  units, scaled with the device's) and for
- *                  binary64 Kuramoto EM with n <= 64 (n = 5: up to 60,000
- *                  orbits, beyond which one orbit per lane is faster),
+ *                  binary64 Kuramoto EM with n <= 64 (n = 5: up to 45,000
+ *                  orbits pairwise or 60,000 mean-field, beyond which one
+ *                  orbit per lane is faster),
  *                  matrix for a supported dense network, else plain.
  *   "shared_params" 0 = p is [orbits][d] (default); 1 = p is one row [d]
  *                  used by every orbit.

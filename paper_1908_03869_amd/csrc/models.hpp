@@ -16,8 +16,15 @@
 #pragma once
 
 #include "devmath.hpp"
+#include "phase64.hpp"
 
 namespace sode {
+
+// sin of a phase difference: in binary64 the coupled kernels' sine
+// (sin_phase64, accurate for |x| up to ~2^20; phases kept continuous, wrap 0,
+// can drift far from [-pi, pi]) below 5e5, the library's beyond.
+__device__ __forceinline__ float pair_sin(float x) { return dev_sin(x); }
+__device__ __forceinline__ double pair_sin(double x) { return fabs(x) < 5e5 ? sin_phase64(x) : dev_sin(x); }
 
 // Stochastic Kuramoto network, Eq. (5)/(6) of Sec. 2.2.1 with the
 // parameter layout p = (K, omega_1..N, p_1..N) of that section's footnote:
@@ -30,12 +37,32 @@ struct Kuramoto {
     __device__ static void drift(int n, R, const R* __restrict__ p, const R* y, R* f)
     {
         const R scale = p[0] / (R)n;
-        for (int i = 0; i < n; ++i) {
-            const R yi = y[i];
-            R coupling = 0;
-            for (int j = 0; j < n; ++j)
-                coupling += dev_sin(y[j] - yi);
-            f[i] = coupling * scale + p[1 + i];
+        // Sizes compiled in (n a constant here): each unordered pair once,
+        // sin(y_i - y_j) = -sin(y_j - y_i) exactly (the difference and both
+        // sines are odd) and the j = i term is sin 0 = 0, with every sum
+        // taking its terms in the order of j as below, so the results are
+        // those of the loop over all pairs.  At a runtime n the arrays live
+        // in scratch memory, where the second write per pair costs more than
+        // the sine it saves: the loop over all pairs.
+        if (__builtin_constant_p(n) && n <= 16) {
+            for (int i = 0; i < n; ++i)
+                f[i] = 0;
+            for (int i = 0; i < n; ++i) {
+                for (int j = i + 1; j < n; ++j) {
+                    const R s = pair_sin(y[j] - y[i]);
+                    f[i] += s;
+                    f[j] -= s;
+                }
+                f[i] = f[i] * scale + p[1 + i];
+            }
+        } else {
+            for (int i = 0; i < n; ++i) {
+                const R yi = y[i];
+                R coupling = 0;
+                for (int j = 0; j < n; ++j)
+                    coupling += pair_sin(y[j] - yi);
+                f[i] = coupling * scale + p[1 + i];
+            }
         }
     }
     template <typename R>

@@ -99,11 +99,12 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
 // until the ensemble fills the chip and ~n^2 per orbit-step after.  Paper
 // protocol (8000 steps) on 256 compute units, scaled with the device's:
 // n = 1 one orbit per lane from 32,768 orbits on (6.5 against 8.7 ms), n = 2
-// from 65,536 (14.0 against 17.0), n = 3 and 4 from 131,072, n = 5 at
-// 262,144 (61.7 against 67.2); from n = 6 the row wins at every size.
+// from 65,536 (14.0 against 17.1), n = 3 from 131,072 (26.6 against 33.7),
+// n = 4 (a size compiled in) from 65,536 (16.2 against 17.1), n = 5 from
+// 131,072 (32.5 against 33.7); from n = 6 the row wins at every size.
 int64_t coupled32_max_orbits(int n)
 {
-    static const int64_t kMax256[6] = {0, 25000, 50000, 90000, 100000, 200000};
+    static const int64_t kMax256[6] = {0, 25000, 50000, 90000, 60000, 120000};
     if (n >= 6)
         return INT64_MAX;
     return kMax256[n] * sode::device_compute_units() / 256;
@@ -113,8 +114,8 @@ int64_t coupled32_max_orbits(int n)
 // Auto follows the paper's speed protocol as measured here.  Binary32: the
 // 16-lane Kuramoto kernel up to coupled32_max_orbits(n), else one orbit per
 // lane.  Binary64: four lanes per orbit for n <= 4 and the 16-lane row for
-// 6 <= n <= 64 at any size; at n = 5 (a row of 11 pads) the row up to 60,000
-// orbits, one orbit per lane beyond.  The dense network goes to the matrix
+// 6 <= n <= 64 at any size; at n = 5 (a row of 11 pads) the row up to 45,000
+// orbits pairwise or 60,000 mean-field, one orbit per lane beyond.  The dense network goes to the matrix
 // kernel; everything else to one orbit per lane.
 int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
 {
@@ -158,13 +159,14 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
         *kernel = 1;
     } else if (coupled_ok && h->precision == 32 && orbits <= coupled32_max_orbits(h->n)) {
         *kernel = 2;
-    } else if (coupled_ok && h->precision == 64 && (h->n != 5 || orbits <= 60000)) {
+    } else if (coupled_ok && h->precision == 64 && (h->n != 5 || orbits <= (h->drift == 1 ? 60000 : 45000))) {
         // Binary64: four lanes per orbit (n <= 4) or a 16-lane row (6 <= n
         // <= 64) beat one orbit per lane at every ensemble size measured
         // (paper protocol, up to 196,608 orbits, pairwise and mean-field).
-        // At n = 5 a row is 11/16 padding and the one-orbit-per-lane kernel,
-        // whose time steps with each whole wave per SIMD, is faster from
-        // 65,536 orbits on (within 3 % of the row where the row wins).
+        // At n = 5 a row is 11/16 padding and the one-orbit-per-lane kernel
+        // is faster from 49,152 orbits on pairwise (41.5 against 44.8 ms)
+        // and 65,536 mean-field (its time steps with each whole wave per
+        // SIMD, so the row wins again at 81,920 mean-field by 7 %).
         *kernel = 2;
     } else if (matrix_ok) {
         *kernel = 3;
