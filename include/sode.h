@@ -196,9 +196,9 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  4 lanes per orbit and DPP quad permutations instead);
  *                  3 = matrix (see "gemm").
  *                  Auto takes coupled for binary32 Kuramoto EM with
- *                  n <= 128 (n <= 5: up to 25,000 / 50,000 / 90,000 /
- *                  60,000 / 120,000 orbits for n = 1..5 on 256 compute
- *                  units, scaled with the device's) and for
+ *                  n <= 128 (n <= 4: up to 56,000 / 120,000 / 200,000 /
+ *                  110,000 orbits for n = 1..4 on 256 compute units,
+ *                  scaled with the device's) and for
  *                  binary64 Kuramoto EM with n <= 64 (n = 5: up to 45,000
  *                  orbits pairwise or 60,000 mean-field, beyond which one
  *                  orbit per lane is faster),

@@ -14,10 +14,12 @@ using namespace coupled32;
 
 // One orbit per 16-lane row, P oscillators per lane; PAD: the system has
 // a.n < 16P oscillators and the rest of the row is padding.  LDS: partner
-// phases through LDS (kLdsPartnerPhases rows only), else by DPP.
-template <int P, bool PAD, bool COMP, bool MF, bool LDS>
+// phases through LDS (kLdsPartnerPhases rows only), else by DPP.  LIM <= 8:
+// a short row of a.n = LIM oscillators, one per lane (lane_coefficients).
+template <int P, bool PAD, bool COMP, bool MF, bool LDS, int LIM = 9>
 __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs a)
 {
+    static_assert(LIM > 8 || (P == 1 && PAD && !MF), "short rows: one padded oscillator per lane, pairwise");
     static_assert(!LDS || kLdsPartnerPhases<P, MF>, "LDS partner phases for rows of 2, 4 or 8, pairwise");
     __shared__ __attribute__((aligned(16))) float lds_phase[LDS ? 256 * P : 1];
     float* const row = LDS ? lds_phase + (threadIdx.x & ~15u) * P : nullptr;
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs
         th[i] = (!PAD || osc < n) ? load_phase(a.X0[o * n + osc]) : 0.0f;
         tl[i] = 0.0f;
     }
-    const LaneCoefficients<P, PAD> c = lane_coefficients<P, PAD>(p, l, a.dt, a.sqdt, a.dt_over_n, n);
+    const LaneCoefficients<P, PAD> c = lane_coefficients<P, PAD>(p, l, a.dt, a.sqdt, a.dt_over_n, n, LIM <= 8);
     const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
 
     save<P, PAD>(a, l, th, c, out_row, 0);
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs
 #pragma unroll
             for (int t = 0; t < B; ++t) {
                 if (t == 0 || j + t < nsteps) {
-                    em_step<P, COMP, MF, PAD, LDS>(th, tl, c, st, k, l, nullptr, xb[t], row);
+                    em_step<P, COMP, MF, PAD, LDS, LIM>(th, tl, c, st, k, l, nullptr, xb[t], row);
                     ++k;
                     if (--to_save == 0) {
                         save<P, PAD>(a, l, th, c, out_row, s);
@@ -69,10 +71,22 @@ __global__ __launch_bounds__(256) void kuramoto_coupled_kernel(const CoupledArgs
     } else {
         for (int64_t s = 1; s < a.nsave; ++s) {
             for (int64_t kk = 0; kk < a.stride; ++kk, ++k)
-                em_step<P, COMP, MF, PAD, LDS>(th, tl, c, st, k, l, nullptr, nullptr, row);
+                em_step<P, COMP, MF, PAD, LDS, LIM>(th, tl, c, st, k, l, nullptr, nullptr, row);
             save<P, PAD>(a, l, th, c, out_row, s);
         }
     }
+}
+
+// Pairwise rows of n <= 8 oscillators, one per lane: the coupling sums
+// leave out the rotations that reach pads only (LIM = n).
+template <int LIM>
+hipError_t launch_short_row(const Request& r, const CoupledArgs& a, dim3 grid, dim3 block)
+{
+    if (r.compensated)
+        hipLaunchKernelGGL((kuramoto_coupled_kernel<1, true, true, false, false, LIM>), grid, block, 0, r.stream, a);
+    else
+        hipLaunchKernelGGL((kuramoto_coupled_kernel<1, true, false, false, false, LIM>), grid, block, 0, r.stream, a);
+    return hipGetLastError();
 }
 
 template <int P, bool PAD, bool LDS>
@@ -82,6 +96,21 @@ hipError_t launch_rows(const Request& r, const CoupledArgs& a)
     const int64_t threads = r.orbits * 16;
     const dim3 block(256);
     const dim3 grid((unsigned)((threads + 255) / 256));
+    if constexpr (P == 1 && PAD) {
+        if (!mf) {
+            switch (r.n) {
+            case 1: return launch_short_row<1>(r, a, grid, block);
+            case 2: return launch_short_row<2>(r, a, grid, block);
+            case 3: return launch_short_row<3>(r, a, grid, block);
+            case 4: return launch_short_row<4>(r, a, grid, block);
+            case 5: return launch_short_row<5>(r, a, grid, block);
+            case 6: return launch_short_row<6>(r, a, grid, block);
+            case 7: return launch_short_row<7>(r, a, grid, block);
+            case 8: return launch_short_row<8>(r, a, grid, block);
+            default: break;
+            }
+        }
+    }
     if (r.compensated && mf)
         hipLaunchKernelGGL((kuramoto_coupled_kernel<P, PAD, true, true, false>), grid, block, 0, r.stream, a);
     else if (r.compensated)

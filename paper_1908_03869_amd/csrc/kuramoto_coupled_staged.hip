@@ -16,7 +16,7 @@ namespace {
 // kuramoto_coupled_kernel.
 // A row past the last orbit (live = false) runs from phase 0 on orbit 0's
 // coefficients and saves nothing.
-template <int P, bool PAD, bool COMP, bool MF>
+template <int P, bool PAD, bool COMP, bool MF, int LIM = 9>
 struct RowOrbit32 {
     static constexpr int kLanes = 16;
     static constexpr int kNormals = P;
@@ -41,7 +41,7 @@ struct RowOrbit32 {
             th[i] = live && (!PAD || osc < n) ? load_phase(a.X0[o * n + osc]) : 0.0f;
             tl[i] = 0.0f;
         }
-        c = lane_coefficients<P, PAD>(p, l, a.dt, a.sqdt, a.dt_over_n, n);
+        c = lane_coefficients<P, PAD>(p, l, a.dt, a.sqdt, a.dt_over_n, n, LIM <= 8);
         st = orbit_stream(oc, a.seed, a.orbit_offset, a.ids, a.seeds);
     }
 
@@ -53,32 +53,59 @@ struct RowOrbit32 {
 
     __device__ __forceinline__ void step(const float (&xi)[P])
     {
-        em_step<P, COMP, MF, PAD>(th, tl, c, st, 0u, l, nullptr, xi);
+        em_step<P, COMP, MF, PAD, false, LIM>(th, tl, c, st, 0u, l, nullptr, xi);
     }
 };
 
-template <int P, bool PAD, bool COMP, bool MF, int NW>
+template <int P, bool PAD, bool COMP, bool MF, int NW, int LIM = 9>
 __global__ __launch_bounds__(64 * (1 + NW)) void kuramoto_coupled_staged_kernel(const CoupledArgs a)
 {
     __shared__ __attribute__((aligned(16))) float stage[2][kStageNormals32];
-    staged_workgroup<RowOrbit32<P, PAD, COMP, MF>, float, kStageNormals32, 4, 16 * P, NW>(a, stage);
+    staged_workgroup<RowOrbit32<P, PAD, COMP, MF, LIM>, float, kStageNormals32, 4, 16 * P, NW>(a, stage);
 }
 
-template <int P, bool PAD, bool COMP, bool MF>
+template <int P, bool PAD, bool COMP, bool MF, int LIM = 9>
 hipError_t launch_staged(const Request& r, const CoupledArgs& a, int nw)
 {
     const dim3 grid((unsigned)((r.orbits + 3) / 4));
     if (nw == 2)
-        hipLaunchKernelGGL((kuramoto_coupled_staged_kernel<P, PAD, COMP, MF, 2>), grid, dim3(192), 0, r.stream, a);
+        hipLaunchKernelGGL((kuramoto_coupled_staged_kernel<P, PAD, COMP, MF, 2, LIM>), grid, dim3(192), 0, r.stream,
+                           a);
     else
-        hipLaunchKernelGGL((kuramoto_coupled_staged_kernel<P, PAD, COMP, MF, 1>), grid, dim3(128), 0, r.stream, a);
+        hipLaunchKernelGGL((kuramoto_coupled_staged_kernel<P, PAD, COMP, MF, 1, LIM>), grid, dim3(128), 0, r.stream,
+                           a);
     return hipGetLastError();
+}
+
+// Pairwise rows of n <= 8 oscillators, one per lane, as in the unstaged
+// kernel: the coupling sums leave out the rotations that reach pads only.
+template <int LIM>
+hipError_t launch_short_row(const Request& r, const CoupledArgs& a, int nw)
+{
+    if (r.compensated)
+        return launch_staged<1, true, true, false, LIM>(r, a, nw);
+    return launch_staged<1, true, false, false, LIM>(r, a, nw);
 }
 
 template <int P, bool PAD>
 hipError_t launch_p(const Request& r, const CoupledArgs& a, int nw)
 {
     const bool mf = r.drift == 1;
+    if constexpr (P == 1 && PAD) {
+        if (!mf) {
+            switch (r.n) {
+            case 1: return launch_short_row<1>(r, a, nw);
+            case 2: return launch_short_row<2>(r, a, nw);
+            case 3: return launch_short_row<3>(r, a, nw);
+            case 4: return launch_short_row<4>(r, a, nw);
+            case 5: return launch_short_row<5>(r, a, nw);
+            case 6: return launch_short_row<6>(r, a, nw);
+            case 7: return launch_short_row<7>(r, a, nw);
+            case 8: return launch_short_row<8>(r, a, nw);
+            default: break;
+            }
+        }
+    }
     if (r.compensated && mf)
         return launch_staged<P, PAD, true, true>(r, a, nw);
     if (r.compensated)

@@ -173,18 +173,21 @@ __device__ __forceinline__ void couple_across(const float (&phi)[P], float (&acc
         acc[b] -= row_rotate<K>(back[b]);
 }
 
-template <int P, int K, bool LDS>
+// Rotations K .. 7 below LIM.
+template <int P, int K, bool LDS, int LIM>
 __device__ __forceinline__ void couple_rotations(const float (&phi)[P], float (&acc)[P], const float* row, int l)
 {
-    if constexpr (K <= 7) {
+    if constexpr (K <= 7 && K < LIM) {
         couple_across<P, K, LDS>(phi, acc, row, l);
-        couple_rotations<P, K + 1, LDS>(phi, acc, row, l);
+        couple_rotations<P, K + 1, LDS, LIM>(phi, acc, row, l);
     }
 }
 
 // LDS: partner phases through row (16 P floats of LDS for this lane's row,
-// aligned to 16 bytes), else by DPP row rotations.
-template <int P, bool LDS = false>
+// aligned to 16 bytes), else by DPP row rotations.  LIM <= 8: only the
+// rotations below LIM and not the opposite lane (short rows, see
+// lane_coefficients).
+template <int P, bool LDS = false, int LIM = 9>
 __device__ __forceinline__ void coupling_sums(const float (&phi)[P], float (&acc)[P], float* row = nullptr,
                                               int l = 0)
 {
@@ -210,7 +213,9 @@ __device__ __forceinline__ void coupling_sums(const float (&phi)[P], float (&acc
             }
         }
     }
-    couple_rotations<P, 1, LDS>(phi, acc, row, l);
+    couple_rotations<P, 1, LDS, LIM>(phi, acc, row, l);
+    if constexpr (LIM <= 8)
+        return;
     // Opposite lane (rotation by 8 is its own inverse).  Pairs (own a,
     // partner b) with a < b are evaluated here and returned to the partner,
     // whose own evaluation covers a > b; a == b (the partner's oscillator of
@@ -260,10 +265,15 @@ struct LaneCoefficients {
 };
 
 // p = (K, omega_1..N, p_1..N) of the N-oscillator system (N = n_real).
+// short_row: one oscillator per lane, N <= 8, coupling sums over the
+// rotations below N only (coupling_sums with LIM = N): lanes N .. 15 are
+// pads, the rotations by N .. 7 and by 8 pair real lanes with pads only,
+// and every real lane meets N - 1 pads (i through its own rotations,
+// N - 1 - i through the pads' returns) instead of 16 - N.
 template <int P, bool PAD = false>
 __device__ __forceinline__ LaneCoefficients<P, PAD> lane_coefficients(const float* __restrict__ p, int l,
                                                                       float dt, float sqdt, float dt_over_n,
-                                                                      int n_real = 16 * P)
+                                                                      int n_real = 16 * P, bool short_row = false)
 {
     LaneCoefficients<P, PAD> c;
     const float kc = p[0] * dt_over_n;
@@ -280,7 +290,7 @@ __device__ __forceinline__ LaneCoefficients<P, PAD> lane_coefficients(const floa
     }
     if constexpr (!PAD)
         c.kc[0] = kc;
-    c.pads = (float)(16 * P - n_real);
+    c.pads = (float)(short_row ? n_real - 1 : 16 * P - n_real);
     return c;
 }
 
@@ -323,7 +333,7 @@ __device__ __forceinline__ void mean_field_sums(const float (&phi)[P], float (&a
 // xi_out (optional) receives the step's P normals; xi_in (optional) supplies
 // them, already drawn (lane_normals_steps), instead of lane_normals.  LDS:
 // pairwise partner phases through `row` (coupling_sums); the same results.
-template <int P, bool COMP, bool MF = false, bool PAD = false, bool LDS = false>
+template <int P, bool COMP, bool MF = false, bool PAD = false, bool LDS = false, int LIM = 9>
 __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const LaneCoefficients<P, PAD>& c,
                                         const Stream& st, uint32_t k, int l, float* xi_out = nullptr,
                                         const float* xi_in = nullptr, float* row = nullptr)
@@ -335,7 +345,7 @@ __device__ __forceinline__ void em_step(float (&th)[P], float (&tl)[P], const La
     if constexpr (MF) {
         mean_field_sums<P, PAD>(phi, acc, c);
     } else {
-        coupling_sums<P, LDS>(phi, acc, row, l);
+        coupling_sums<P, LDS, LIM>(phi, acc, row, l);
         if constexpr (PAD) {
 #pragma unroll
             for (int i = 0; i < P; ++i)

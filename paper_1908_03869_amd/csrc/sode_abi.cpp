@@ -93,19 +93,19 @@ int check_adjoint_args(const sode_ctx* h, int64_t orbits, double dt, int64_t nst
     return SODE_OK;
 }
 
-// Largest binary32 Kuramoto ensemble (n <= 5) for which the 16-lane row, a
-// padded one, beats one orbit per lane: the row costs the same per orbit for
-// any n <= 16, while one orbit per lane takes a fixed, latency-bound time
-// until the ensemble fills the chip and ~n^2 per orbit-step after.  Paper
-// protocol (8000 steps) on 256 compute units, scaled with the device's:
-// n = 1 one orbit per lane from 32,768 orbits on (6.5 against 8.7 ms), n = 2
-// from 65,536 (14.0 against 17.1), n = 3 from 131,072 (26.6 against 33.7),
-// n = 4 (a size compiled in) from 65,536 (16.2 against 17.1), n = 5 from
-// 131,072 (32.5 against 33.7); from n = 6 the row wins at every size.
+// Largest binary32 Kuramoto ensemble (n <= 4) for which the 16-lane row, a
+// padded one, beats one orbit per lane: a short row (n <= 8) costs ~n per
+// orbit, while one orbit per lane takes a fixed, latency-bound time until
+// the ensemble fills the chip and ~n^2 per orbit-step after.  Paper protocol
+// (8000 steps) on 256 compute units, scaled with the device's: n = 1 one
+// orbit per lane from 65,536 orbits on (6.7 against 7.3 ms), n = 2 from
+// 131,072 (15.3 against 16.2), n = 3 at 262,144 (32.9 against 37.3), n = 4
+// (a size compiled in) from 131,072 (18.1 against 20.9); from n = 5 the row
+// wins at every size measured (n = 5 at 262,144 orbits 46.2 against 50.5).
 int64_t coupled32_max_orbits(int n)
 {
-    static const int64_t kMax256[6] = {0, 25000, 50000, 90000, 60000, 120000};
-    if (n >= 6)
+    static const int64_t kMax256[5] = {0, 56000, 120000, 200000, 110000};
+    if (n >= 5)
         return INT64_MAX;
     return kMax256[n] * sode::device_compute_units() / 256;
 }

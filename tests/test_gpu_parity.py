@@ -444,14 +444,14 @@ def test_coupled_fp32_lds_and_dpp_partner_reads_bitwise(gpu, n, lds_rows, dpp_ro
         np.testing.assert_array_equal(out_big[big - 3:], out_tail)
 
 
-@pytest.mark.parametrize("n,orbits_per_cu,expect", [(1, 128, "plain"), (2, 256, "plain"), (4, 128, "coupled"),
-                                                    (4, 256, "plain"),
-                                                    (5, 1024, "plain"), (6, 1024, "coupled"), (2, 64, "coupled")])
+@pytest.mark.parametrize("n,orbits_per_cu,expect", [(1, 128, "coupled"), (1, 256, "plain"), (2, 512, "plain"),
+                                                    (4, 256, "coupled"), (4, 512, "plain"), (5, 1024, "coupled"),
+                                                    (6, 1024, "coupled"), (2, 64, "coupled")])
 def test_auto_selection_binary32(gpu, n, orbits_per_cu, expect):
-    """Binary32 auto selection: the 16-lane row for n >= 6 at any size and
-    for n <= 5 up to a measured ensemble size (25,000 / 50,000 / 90,000 /
-    60,000 / 120,000 orbits for n = 1..5 on 256 compute units, scaled with
-    the device's), else one orbit per lane.  The auto result equals the
+    """Binary32 auto selection: the 16-lane row for n >= 5 at any size and
+    for n <= 4 up to a measured ensemble size (56,000 / 120,000 / 200,000 /
+    110,000 orbits for n = 1..4 on 256 compute units, scaled with the
+    device's), else one orbit per lane.  The auto result equals the
     expected kernel's result bit for bit."""
     import torch
 
