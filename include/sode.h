@@ -199,7 +199,7 @@ int sode_build_log(sode_t h, char* buf, size_t len, size_t* needed);
  *                  n <= 128 (n <= 4: up to 56,000 / 120,000 / 200,000 /
  *                  110,000 orbits for n = 1..4 on 256 compute units,
  *                  scaled with the device's) and for
- *                  binary64 Kuramoto EM with n <= 64 (n = 5: up to 45,000
+ *                  binary64 Kuramoto EM with n <= 64 (n = 5: up to 100,000
  *                  orbits pairwise or 60,000 mean-field, beyond which one
  *                  orbit per lane is faster),
  *                  matrix for a supported dense network, else plain.

@@ -61,12 +61,14 @@ __device__ __forceinline__ double wrap64(double x)
 
 __device__ __forceinline__ double load_phase64(double x) { return fabs(x) <= kPi ? x : wrap64(x); }
 
-// Pairs between this lane and the lane K rotations away (K = 1..7): this
-// lane evaluates them and returns the negated partial sums with the inverse
-// rotation.
-template <int P, int K>
+// Pairs between this lane and the lane K rotations away (K = 1..7, below
+// LIM): this lane evaluates them and returns the negated partial sums with
+// the inverse rotation.
+template <int P, int K, int LIM>
 __device__ __forceinline__ void couple_across64(const double (&th)[P], double (&acc)[P])
 {
+    if constexpr (K >= LIM)
+        return;
     double other[P], back[P];
 #pragma unroll
     for (int b = 0; b < P; ++b)
@@ -84,11 +86,13 @@ __device__ __forceinline__ void couple_across64(const double (&th)[P], double (&
     for (int b = 0; b < P; ++b)
         acc[b] -= row_rotate64<K>(back[b]);
     if constexpr (K < 7)
-        couple_across64<P, K + 1>(th, acc);
+        couple_across64<P, K + 1, LIM>(th, acc);
 }
 
 // sum_j sin(theta_j - theta_i) for the lane's P oscillators (pads included).
-template <int P>
+// LIM <= 8: only the rotations below LIM and not the opposite lane (short
+// rows, see RowOrbit64).
+template <int P, int LIM = 9>
 __device__ __forceinline__ void coupling_sums64(const double (&th)[P], double (&acc)[P])
 {
     if constexpr (P == 1) {
@@ -104,7 +108,9 @@ __device__ __forceinline__ void coupling_sums64(const double (&th)[P], double (&
             }
         }
     }
-    couple_across64<P, 1>(th, acc);
+    couple_across64<P, 1, LIM>(th, acc);
+    if constexpr (LIM <= 8)
+        return;
     // Opposite lane (rotation by 8, its own inverse): pairs (own a, partner
     // b) with a < b here, returned to the partner, which covers a > b; a = b
     // by both lanes, each for its own side.
@@ -258,9 +264,14 @@ __device__ __forceinline__ double quad_sum64(double v)
 // their per-oscillator constants (omega dt, p sqrt(dt), K dt / N, weight 0
 // for pads), the save of the state or of r, and one Euler-Maruyama step
 // with given normals.  A row past the last orbit (live = false) runs on
-// zeros and saves nothing; it reads no input.
-template <int P, bool PAD, bool MF>
+// zeros and saves nothing; it reads no input.  LIM <= 8: a short row of
+// a.n = LIM oscillators, one per lane: lanes LIM .. 15 are pads, the
+// rotations by LIM .. 7 and by 8 pair real lanes with pads only and are left
+// out, and every real lane meets LIM - 1 pads (i through its own rotations,
+// LIM - 1 - i through the pads' returns) instead of 16 - LIM.
+template <int P, bool PAD, bool MF, int LIM = 9>
 struct RowOrbit64 {
+    static_assert(LIM > 8 || (P == 1 && PAD && !MF), "short rows: one padded oscillator per lane, pairwise");
     static constexpr int kLanes = 16;  // lanes per orbit
     static constexpr int kNormals = P; // normals per lane and step
     double th[P], drift0[P], noise[P], kc[P], w[P];
@@ -287,7 +298,7 @@ struct RowOrbit64 {
             kc[i] = real ? kcv : 0.0;
             w[i] = real ? 1.0 : 0.0;
         }
-        pads = (double)(16 * P - n);
+        pads = (double)(LIM <= 8 ? n - 1 : 16 * P - n);
     }
 
     __device__ __forceinline__ void save(const Coupled64Args& a, int64_t s)
@@ -327,7 +338,7 @@ struct RowOrbit64 {
             for (int i = 0; i < P; ++i)
                 acc[i] = cs[i] * S - sn[i] * C;
         } else {
-            coupling_sums64<P>(th, acc);
+            coupling_sums64<P, LIM>(th, acc);
             if constexpr (PAD) {
 #pragma unroll
                 for (int i = 0; i < P; ++i)
@@ -408,14 +419,14 @@ struct QuadOrbit64 {
 // steps at a time where lanes share a Philox block), one orbit per row or
 // quad, 256-thread blocks.  Whole rows and quads are in or out together, so
 // no lane permutation reads a finished lane.
-template <int P, bool PAD, bool MF>
+template <int P, bool PAD, bool MF, int LIM = 9>
 __global__ __launch_bounds__(256) void kuramoto_coupled64_kernel(const Coupled64Args a)
 {
     const int l = threadIdx.x & 15;
     const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     if (o >= a.orbits)
         return;
-    RowOrbit64<P, PAD, MF> f(a, o, l, true);
+    RowOrbit64<P, PAD, MF, LIM> f(a, o, l, true);
     const Stream st = orbit_stream(o, a.seed, a.orbit_offset, a.ids, a.seeds);
     f.save(a, 0);
     uint32_t k = (uint32_t)a.step_offset;
@@ -518,6 +529,19 @@ hipError_t launch_quad64(const Request& r, const Coupled64Args& a)
     return hipGetLastError();
 }
 
+// Pairwise rows of 5 <= n <= 8 oscillators, one per lane, staged or not:
+// the coupling sums leave out the rotations that reach pads only (LIM = n).
+template <int LIM>
+hipError_t launch_short_row64(const Request& r, const Coupled64Args& a)
+{
+    const int nw = staged_noise_waves(r, (r.orbits + 3) / 4);
+    if (nw > 0)
+        return launch_staged64<RowOrbit64<1, true, false, LIM>, 4, 16>(r, a, nw);
+    const dim3 grid((unsigned)((r.orbits * 16 + 255) / 256));
+    hipLaunchKernelGGL((kuramoto_coupled64_kernel<1, true, false, LIM>), grid, dim3(256), 0, r.stream, a);
+    return hipGetLastError();
+}
+
 template <int P, bool PAD>
 hipError_t launch_p64(const Request& r)
 {
@@ -541,6 +565,17 @@ hipError_t launch_p64(const Request& r)
     a.nonfinite = r.nonfinite;
     if (P == 1 && r.n <= 4)  // four lanes per orbit
         return r.n == 4 ? launch_quad64<false>(r, a) : launch_quad64<true>(r, a);
+    if constexpr (P == 1 && PAD) {
+        if (r.drift != 1) {
+            switch (r.n) {
+            case 5: return launch_short_row64<5>(r, a);
+            case 6: return launch_short_row64<6>(r, a);
+            case 7: return launch_short_row64<7>(r, a);
+            case 8: return launch_short_row64<8>(r, a);
+            default: break;
+            }
+        }
+    }
     if constexpr (P == 1 || P == 2 || P == 4) {
         const int nw = staged_noise_waves(r, (r.orbits + 3) / 4);
         if (nw > 0)

@@ -114,7 +114,7 @@ int64_t coupled32_max_orbits(int n)
 // Auto follows the paper's speed protocol as measured here.  Binary32: the
 // 16-lane Kuramoto kernel up to coupled32_max_orbits(n), else one orbit per
 // lane.  Binary64: four lanes per orbit for n <= 4 and the 16-lane row for
-// 6 <= n <= 64 at any size; at n = 5 (a row of 11 pads) the row up to 45,000
+// 6 <= n <= 64 at any size; at n = 5 (a row of 11 pads) the row up to 100,000
 // orbits pairwise or 60,000 mean-field, one orbit per lane beyond.  The dense network goes to the matrix
 // kernel; everything else to one orbit per lane.
 int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
@@ -159,14 +159,15 @@ int choose_kernel(const sode_ctx* h, int64_t orbits, int* kernel)
         *kernel = 1;
     } else if (coupled_ok && h->precision == 32 && orbits <= coupled32_max_orbits(h->n)) {
         *kernel = 2;
-    } else if (coupled_ok && h->precision == 64 && (h->n != 5 || orbits <= (h->drift == 1 ? 60000 : 45000))) {
+    } else if (coupled_ok && h->precision == 64 && (h->n != 5 || orbits <= (h->drift == 1 ? 60000 : 100000))) {
         // Binary64: four lanes per orbit (n <= 4) or a 16-lane row (6 <= n
         // <= 64) beat one orbit per lane at every ensemble size measured
         // (paper protocol, up to 196,608 orbits, pairwise and mean-field).
-        // At n = 5 a row is 11/16 padding and the one-orbit-per-lane kernel
-        // is faster from 49,152 orbits on pairwise (41.5 against 44.8 ms)
-        // and 65,536 mean-field (its time steps with each whole wave per
-        // SIMD, so the row wins again at 81,920 mean-field by 7 %).
+        // At n = 5 a row is 11/16 padding and the one-orbit-per-lane kernel,
+        // whose time steps with each whole wave per SIMD, is faster from
+        // about 100,000 orbits on pairwise (131,072: 60.0 against 81.8 ms;
+        // the short row wins at 81,920, 51.6 against 59.7) and 65,536
+        // mean-field (47.7 against 55.1).
         *kernel = 2;
     } else if (matrix_ok) {
         *kernel = 3;

@@ -121,11 +121,11 @@ def test_noise_waves_bitwise(gpu, n, obs, drift):
 
 
 @pytest.mark.parametrize("n,orbits,expect", [(6, 98304, "coupled"), (17, 2048, "coupled"),
-                                             (5, 49152, "plain"), (5, 4096, "coupled")])
+                                             (5, 131072, "plain"), (5, 49152, "coupled"), (5, 4096, "coupled")])
 def test_auto_selection_binary64(gpu, n, orbits, expect):
     """Auto selection in binary64 takes the 16-lane row for every n in 6..64
     at any ensemble size and, at n = 5 (a row of 11 pads), one orbit per lane
-    beyond 45,000 orbits (pairwise): the auto result equals the expected kernel's
+    beyond 100,000 orbits (pairwise): the auto result equals the expected kernel's
     result bit for bit (the two kernels sum in different orders)."""
     rng = np.random.default_rng(700 + n)
     X0 = rng.uniform(-np.pi, np.pi, (orbits, n))
